@@ -1,0 +1,35 @@
+"""CPU oracle for the selected inverse and the fermionic drift.
+
+TEST INFRASTRUCTURE ONLY. Only the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark may import or call anything in this package. The GPU library
+never routes through it, and it shares no code with the GPU library: only the
+seeded input generator (paper_1707_08874_amd.inputs) feeds both sides.
+
+What it computes, by plain definition (Sec. 3 of the paper):
+
+* the staggered Dirac matrix D(m, mu) assembled densely (or as a sparse matrix for
+  the Krylov column solves) from the links,
+* Z = D^{-1} by LAPACK (zgetrf + zgetri through numpy.linalg.inv): the selected
+  inversion reaches exactly these entries up to rounding (Sec. 3, the passage on
+  selected inversion being exact on the nonzero pattern of D),
+* the nine 3x3 blocks of Z on the nonzero pattern of D for every site,
+* the drift K_{a,x,nu} = tr[D^{-1} d_{a,x,nu} D] (Eq. 6) through the two-block
+  reduction tr(P B) + tr(Q F) (Eq. 8), with the derivative blocks F, B formed
+  explicitly from the Gell-Mann matrices.
+
+Pins: see tests/test_oracle_pins.py. Every function here is pinned by at least
+one test that does not reuse the function's own formula.
+"""
+from .staggered import (coords, eta_phases, hop_tables, dirac_dense, dirac_sparse,
+                        link_derivative_blocks)
+from .selinv import (gell_mann, inverse_dense, selected_blocks, drift_from_blocks,
+                     selected_and_drift, SLOT_NAMES)
+from .observables import chiral_condensate, number_density
+from .columns import inverse_columns, sampled_selected_check
+
+__all__ = [
+    "coords", "eta_phases", "hop_tables", "dirac_dense", "dirac_sparse",
+    "link_derivative_blocks", "gell_mann", "inverse_dense", "selected_blocks",
+    "drift_from_blocks", "selected_and_drift", "SLOT_NAMES", "chiral_condensate",
+    "number_density", "inverse_columns", "sampled_selected_check",
+]
