@@ -1,0 +1,141 @@
+/*
+ * clsel — selected inversion of the staggered Dirac matrix and the exact
+ * complex-Langevin fermion drift, on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Bloch & Schenk, "Selected inversion as key to a stable Langevin
+ * evolution across the QCD phase boundary", Lattice 2017):
+ *   given SL(3,C) links U_{x,nu}, a quark mass m and a chemical potential mu,
+ *   compute the entries of D(m,mu)^{-1} on the nonzero pattern of D (Sec. 3,
+ *   selected-inversion paragraph) and the fermionic drift
+ *   K^f_{a,x,nu} = tr[D^{-1} d_{a,x,nu} D] (Eq. 6) for every link, through the
+ *   two-block reduction K = tr(P B) + tr(Q F) (Eq. 8).
+ *
+ * Operator (the paper names it only as the staggered operator of Eq. 1):
+ *   D_{x,x} = m; D_{x,x+nu} = +1/2 eta_nu(x) s_nu(x) e^{+mu delta_{nu,3}} U_{x,nu};
+ *   D_{x+nu,x} = -1/2 eta_nu(x) s_nu(x) e^{-mu delta_{nu,3}} U_{x,nu}^{-1};
+ *   eta_nu(x) = (-1)^{x_0+...+x_{nu-1}}; s = -1 on the temporal hop that wraps
+ *   (antiperiodic time), +1 otherwise; spatial directions periodic.
+ * Derivative: left Lie derivative U -> e^{i alpha lambda_a} U (matches the
+ * Langevin update U <- R U of Eqs. 3-4); lambda_a the Gell-Mann matrices.
+ *
+ * Layouts (all complex128 = two doubles, re then im, row-major colour indices):
+ *   site index     x = x0 + L0*(x1 + L1*(x2 + L2*x3)), x3 = time
+ *   links          [B][V][4][3][3]
+ *   selected       [B][V][9][3][3]; slot 0 = Z_{x,x}, 1+nu = Z_{x,x+nu},
+ *                  5+nu = Z_{x,x-nu}  (nu = 0..3)
+ *   drift          [B][V][4][8]; component a-1 of K_{a,x,nu}
+ *
+ * Memory: device pointers are caller-owned and must stay valid until the work
+ * enqueued on the batch's stream has passed them. Plans and batches own all
+ * other memory. A batch references its plan: destroy batches first.
+ *
+ * Errors: functions return 0 (CL_OK) or a negative CL_E* code; cl_last_error()
+ * gives a message. Numeric failures inside the enqueued work are recorded per
+ * configuration and reported by cl_status; the outputs of a failed
+ * configuration are NaN. There is one GPU code path and no CPU fallback: without
+ * a usable gfx950 device every numeric call fails with CL_ENODEV or CL_EHIP.
+ */
+#ifndef CLSEL_H
+#define CLSEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CL_OK 0
+#define CL_EINVAL (-1)      /* bad argument: odd or < 4 extent, null pointer, batch < 1 */
+#define CL_ENOMEM (-2)      /* device or host allocation failed */
+#define CL_EORDER (-3)      /* call out of order, e.g. cl_selinv before cl_factor */
+#define CL_ESINGULAR (-4)   /* zero or non-finite pivot inside a supernode (per config) */
+#define CL_ENONFINITE (-5)  /* non-finite or singular link (per config) */
+#define CL_EHIP (-6)        /* a HIP runtime call failed */
+#define CL_ENODEV (-7)      /* no usable GPU */
+
+typedef struct cl_plan_s* cl_plan;
+typedef struct cl_batch_s* cl_batch;
+
+/* Options of the symbolic analysis. Zero fields take the defaults. */
+typedef struct {
+  int32_t leaf_sites;     /* nested dissection stops at boxes of <= this many sites (default 4) */
+  int32_t max_pivot_rows; /* separators with more rows are split into a chain (<= 1536, default 1536) */
+  int32_t nb;             /* block width of the frontal Gauss-Jordan sweep (1..64, default 64) */
+} cl_plan_opts;
+
+typedef struct {
+  int32_t dims[4];
+  int64_t volume;          /* V */
+  int64_t n;               /* N = 3V */
+  int32_t nfronts, nlevels, max_steps, max_front_rows, max_pivot_rows;
+  int64_t pool_elems;      /* complex elements of one front pool, per configuration */
+  double flops_factor;     /* executed by the factorisation kernels, per configuration */
+  double flops_selinv;     /* executed by the selected-inversion kernels */
+  double flops_factor_alg; /* standard block LU count: 8/3 p^3 + 8 s p^2 + 8 s^2 p per supernode */
+  double flops_selinv_alg; /* standard selected inversion: 16/3 p^3 + 8 p^2 s + 16 s^2 p */
+  double flops_dense_inverse; /* 8 N^3: what a full inverse would cost */
+} cl_plan_info_t;
+
+/* Symbolic analysis of one lattice shape (host only, no device work). Every
+ * extent must be even and >= 4. The plan is immutable and may be shared by any
+ * number of batches and threads. Sec. 3: sparse LU followed by selected
+ * inversion; the ordering is geometric nested dissection. */
+int cl_symbolic(const int32_t dims[4], cl_plan* out);
+int cl_symbolic_ex(const int32_t dims[4], const cl_plan_opts* opts, cl_plan* out);
+int cl_plan_info(cl_plan plan, cl_plan_info_t* out);
+/* Device bytes a batch of `batch` configurations needs (for admission control). */
+size_t cl_plan_bytes(cl_plan plan, int32_t batch);
+/* Copies one plan table to host memory for inspection: what = 0 fronts (int64
+ * rows of CL_FRONT_FIELDS), 1 front sites (int32), 2 parent->child row maps
+ * (int32), 3 child->parent row maps (int32), 4 selected-block offsets (int64),
+ * 5 elimination order (int64). With dst == NULL only *nbytes is set. */
+#define CL_FRONT_FIELDS 28
+int cl_plan_export(cl_plan plan, int32_t what, void* dst, size_t* nbytes);
+void cl_plan_destroy(cl_plan plan);
+
+/* Numeric workspace for up to `batch` configurations of one plan. Work is
+ * ordered after, and before, work on `hip_stream` (NULL = the null stream); the
+ * batch runs it on a private stream of default priority. */
+int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out);
+/* Configurations processed by the following calls: 1..batch (default batch). */
+int cl_batch_set_active(cl_batch batch, int32_t n);
+/* Enables (1) or disables (0) HIP-graph capture of cl_run. */
+int cl_batch_use_graph(cl_batch batch, int32_t enable);
+/* Assembles D for each configuration from `links_dev` (device, [B][V][4][3][3]
+ * complex128, copied before the call returns control of it to the stream) and
+ * m_host[b], mu_host[b], then runs the supernodal factorisation (partial
+ * pivoting inside each supernode's own rows). Enqueues only. */
+int cl_factor(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host);
+/* Selected inversion (Takahashi / Erisman-Tinney recurrences in supernodal form):
+ * the blocks of D^{-1} on the filled pattern, root to leaves. Enqueues only. */
+int cl_selinv(cl_batch batch);
+/* Drift K [B][V][4][8] complex128 into out_dev (device). Enqueues only. */
+int cl_drift(cl_batch batch, void* out_dev);
+/* Selected blocks [B][V][9][3][3] complex128 into out_dev (device). Enqueues only. */
+int cl_selected(cl_batch batch, void* out_dev);
+/* cl_factor + cl_selinv + cl_selected + cl_drift in one call; replayed from a
+ * HIP graph when enabled. Either output pointer may be NULL. */
+int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host,
+           void* selected_out_dev, void* drift_out_dev);
+/* Waits for the batch's work and copies one status per active configuration:
+ * 0, CL_ESINGULAR or CL_ENONFINITE. Returns 0 or an API error. */
+int cl_status(cl_batch batch, int32_t* per_config_host);
+/* Measurement support: with profiling on (eager path only), every launch of the
+ * complex GEMM kernel is bracketed by HIP events on the batch stream. _read waits
+ * for the stream, returns the summed kernel time (ms), the summed algorithmic flops
+ * (8*M*N*K per product) and the number of timed launches since the last read, and
+ * resets the counters. */
+int cl_batch_profile(cl_batch batch, int32_t enable);
+int cl_batch_profile_read(cl_batch batch, double* gemm_ms, double* gemm_flops, int64_t* launches);
+/* Waits for all work of the batch. */
+int cl_batch_sync(cl_batch batch);
+void cl_batch_destroy(cl_batch batch);
+
+const char* cl_strerror(int code);
+const char* cl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CLSEL_H */

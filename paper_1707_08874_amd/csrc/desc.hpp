@@ -1,0 +1,74 @@
+// Launch descriptors shared by the host runtime and the HIP kernels.
+//
+// Every numeric buffer is complex128 stored as double2 (re, im). Per configuration b
+// the library keeps:
+//   fronts : 2 pools of pool_elems elements each (ping-pong during the frontal
+//            Gauss-Jordan sweep; the selected-inverse front goes to the pool the
+//            factorised front does not occupy), config stride 2*pool_elems;
+//   ws     : complex workspace of ws_elems elements (panel copies, pivot-block
+//            inverses, transformed pivot rows);
+//   iws    : int32 workspace of iws_elems entries (pivot lists, row maps, row ids).
+#pragma once
+#include <cstdint>
+
+namespace clsel {
+
+// Pool selectors for plain GEMM operands.
+enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2 };
+
+// Front assembly: one entry per (front) of a level.
+struct AsmDesc {
+  int64_t off;            // front offset (pool 0 receives the assembled front)
+  int64_t site_off;       // into front_sites
+  int64_t blk_start;      // first 256-element block of this front in the launch
+  int H, p, ld, nchild;
+  int64_t inv_off[4];     // per child: H entries (parent row -> child update row)
+  int64_t child_off[4];   // child front offset, already including its pool
+  int child_p[4];
+  int child_ld[4];
+  int64_t rowid_off;      // iws: p entries initialised to the identity
+};
+
+// Panel of the frontal Gauss-Jordan sweep: one entry per (front, block step).
+struct PanelDesc {
+  int64_t x_off;          // front offset in the input pool (incl. pool)
+  int64_t pw_off;         // ws: (p-k) x nb panel copy
+  int64_t pinv_off;       // ws: nb x nb inverse of the pivot block
+  int64_t piv_off;        // iws: nb pivot rows (rows of the input front)
+  int64_t rmap_off;       // iws: H entries, new row -> old row
+  int64_t rowid_off;      // iws: p entries, equation currently at each pivot row
+  int H, p, ld, k, nbk;
+};
+
+// GEMM problem. mode 0: C = alpha*A*B (+ C0); mode 1: transformed pivot rows
+// Rt = Pinv * [X rows piv | identity on the panel]; mode 2: front update
+// Y = base - A*Rt with A the panel columns of X (pivot rows replaced by -e_t).
+struct GemmDesc {
+  int mode;
+  int M, N, K;
+  int tiles_n;
+  int64_t tile_start;     // first tile of this problem within the launch
+  // mode 0
+  int a_pool, b_pool, c_pool, c0_pool;
+  int64_t a_off, b_off, c_off, c0_off;
+  int lda, ldb, ldc, ldc0;
+  double alpha;
+  int has_c0;
+  // modes 1, 2
+  int k, nbk, p, ld, last;
+  int64_t x_off, y_off;   // input / output front (incl. pool)
+  int64_t rt_off;         // ws: nbk x H transformed pivot rows (ld = H)
+  int64_t pinv_off;       // ws
+  int64_t piv_off, rmap_off, rowid_off;  // iws
+};
+
+// Gather of the update-set block of the selected inverse from the parent front.
+struct GatherDesc {
+  int64_t z_off;          // this front's Z front (incl. pool)
+  int64_t par_off;        // parent's Z front (incl. pool)
+  int64_t rel_off;        // s entries
+  int64_t blk_start;
+  int p, s, ld, par_ld;
+};
+
+}  // namespace clsel

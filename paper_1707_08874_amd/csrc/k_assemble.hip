@@ -1,0 +1,111 @@
+// Link inverses and front assembly.
+//
+// The staggered operator (hopping blocks c+ U and -c- U^{-1}, Sec. 2, Eq. 1, with the
+// explicit form fixed in the project docs) is never stored as a sparse matrix: each
+// front pulls the entries it owns straight from the links, plus the update (Schur)
+// blocks of its children, in one deterministic pass (no atomics).
+#include "desc.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace clsel {
+
+// U^{-1} = adj(U) / det(U) for every link of every configuration. SL(3,C) links are
+// not unitary, so the inverse is computed exactly rather than as U^dagger.
+__global__ void k_link_inverse(const double2* __restrict__ links, double2* __restrict__ linv,
+                               int64_t links_per_cfg, int nbatch, int32_t* __restrict__ status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= links_per_cfg * nbatch) return;
+  const double2* u = links + i * 9;
+  double2 a[9];
+  bool finite = true;
+  for (int k = 0; k < 9; ++k) {
+    a[k] = u[k];
+    finite = finite && isfinite(a[k].x) && isfinite(a[k].y);
+  }
+  // cofactors C_rc
+  const double2 c00 = csub(cmul(a[4], a[8]), cmul(a[5], a[7]));
+  const double2 c01 = csub(cmul(a[5], a[6]), cmul(a[3], a[8]));
+  const double2 c02 = csub(cmul(a[3], a[7]), cmul(a[4], a[6]));
+  const double2 c10 = csub(cmul(a[2], a[7]), cmul(a[1], a[8]));
+  const double2 c11 = csub(cmul(a[0], a[8]), cmul(a[2], a[6]));
+  const double2 c12 = csub(cmul(a[1], a[6]), cmul(a[0], a[7]));
+  const double2 c20 = csub(cmul(a[1], a[5]), cmul(a[2], a[4]));
+  const double2 c21 = csub(cmul(a[2], a[3]), cmul(a[0], a[5]));
+  const double2 c22 = csub(cmul(a[0], a[4]), cmul(a[1], a[3]));
+  const double2 det = cadd(cadd(cmul(a[0], c00), cmul(a[1], c01)), cmul(a[2], c02));
+  if (!finite || cabs2(det) == 0.0) atomicMin(&status[i / links_per_cfg], kStatusNonFinite);
+  double2* o = linv + i * 9;
+  // inverse = transpose of the cofactor matrix / det
+  o[0] = cdiv(c00, det); o[1] = cdiv(c10, det); o[2] = cdiv(c20, det);
+  o[3] = cdiv(c01, det); o[4] = cdiv(c11, det); o[5] = cdiv(c21, det);
+  o[6] = cdiv(c02, det); o[7] = cdiv(c12, det); o[8] = cdiv(c22, det);
+}
+
+// Entry D_{(x,a),(y,b)} of the staggered operator.
+__device__ double2 dirac_entry(int64_t x, int a, int64_t y, int b, const double2* __restrict__ U,
+                               const double2* __restrict__ Uinv, double m, double emu,
+                               double emu_inv, const LatticeDims& dims) {
+  if (x == y) return make_double2(a == b ? m : 0.0, 0.0);
+  int cx[4], cy[4];
+  dcoords(x, dims, cx);
+  dcoords(y, dims, cy);
+  int ndiff = 0, nu = -1;
+  for (int k = 0; k < 4; ++k)
+    if (cx[k] != cy[k]) { ++ndiff; nu = k; }
+  if (ndiff != 1) return make_double2(0.0, 0.0);
+  const int L = dims.L[nu];
+  if (cy[nu] == (cx[nu] + 1) % L) {  // y = x + nu: +c+(x,nu) U_{x,nu}
+    const double cp = dcplus(cx, nu, dims, emu);
+    return cscale(U[(x * 4 + nu) * 9 + a * 3 + b], cp);
+  }
+  if (cx[nu] == (cy[nu] + 1) % L) {  // x = y + nu: -c-(y,nu) U_{y,nu}^{-1}
+    const double cm = dcminus(cy, nu, dims, emu_inv);
+    return cscale(Uinv[(y * 4 + nu) * 9 + a * 3 + b], -cm);
+  }
+  return make_double2(0.0, 0.0);
+}
+
+// One thread per front element. Front entry (I, J) = sum over children of the
+// child's update block at the mapped position + the entry of D if row I or column J
+// is a pivot of this front (entries between two update rows belong to ancestors).
+__global__ void __launch_bounds__(256)
+k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ fronts,
+           int64_t cfg_stride, const int32_t* __restrict__ front_sites,
+           const int32_t* __restrict__ inv_maps, const double2* __restrict__ links,
+           const double2* __restrict__ linv, int64_t link_cfg_stride,
+           const double* __restrict__ mvals, const double* __restrict__ muvals, LatticeDims dims,
+           int32_t* __restrict__ iws, int64_t iws_stride) {
+  const int b = blockIdx.y;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {  // last desc with blk_start <= blockIdx.x
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].blk_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const AsmDesc& d = descs[lo];
+  const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
+  const int64_t HH = (int64_t)d.H * d.H;
+  if (e >= HH) return;
+  const int I = (int)(e / d.H), J = (int)(e % d.H);
+  double2* F = fronts + b * cfg_stride;
+  double2 v = make_double2(0.0, 0.0);
+  for (int c = 0; c < d.nchild; ++c) {
+    const int ii = inv_maps[d.inv_off[c] + I];
+    const int jj = inv_maps[d.inv_off[c] + J];
+    if (ii >= 0 && jj >= 0) {
+      const int cp = d.child_p[c];
+      v = cadd(v, F[d.child_off[c] + (int64_t)(cp + ii) * d.child_ld[c] + cp + jj]);
+    }
+  }
+  if (I < d.p || J < d.p) {
+    const int64_t x = front_sites[d.site_off + I / 3];
+    const int64_t y = front_sites[d.site_off + J / 3];
+    const double mu = muvals[b];
+    v = cadd(v, dirac_entry(x, I % 3, y, J % 3, links + b * link_cfg_stride,
+                            linv + b * link_cfg_stride, mvals[b], exp(mu), exp(-mu), dims));
+  }
+  F[d.off + (int64_t)I * d.ld + J] = v;
+  if (e < d.p) iws[b * iws_stride + d.rowid_off + e] = (int32_t)e;
+}
+
+}  // namespace clsel

@@ -1,0 +1,104 @@
+// Data movement of the selected inversion and the drift contraction.
+#include "desc.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace clsel {
+
+// Z_SS of a front = the entries of its parent's selected-inverse front at the
+// update rows (the update set of a front is a clique of the filled pattern and
+// lies inside the parent front, so one relative map suffices).
+__global__ void __launch_bounds__(256)
+k_gather_zss(const GatherDesc* __restrict__ descs, int ndesc, double2* __restrict__ fronts,
+             int64_t cfg_stride, const int32_t* __restrict__ rel_maps) {
+  const int b = blockIdx.y;
+  int lo = 0, hi = ndesc - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (descs[mid].blk_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const GatherDesc& d = descs[lo];
+  const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
+  if (e >= (int64_t)d.s * d.s) return;
+  const int a = (int)(e / d.s), c = (int)(e % d.s);
+  double2* F = fronts + b * cfg_stride;
+  const int ra = rel_maps[d.rel_off + a], rc = rel_maps[d.rel_off + c];
+  F[d.z_off + (int64_t)(d.p + a) * d.ld + d.p + c] = F[d.par_off + (int64_t)ra * d.par_ld + rc];
+}
+
+// Selected blocks on the pattern of D: out[b][x][slot][3][3], slot 0 = (x,x),
+// 1+nu = (x,x+nu), 5+nu = (x,x-nu). Configurations with a failed factorisation
+// get NaN.
+__global__ void __launch_bounds__(256)
+k_gather_selected(const double2* __restrict__ fronts, int64_t cfg_stride,
+                  const int64_t* __restrict__ sel_off, const int32_t* __restrict__ sel_ld,
+                  int64_t V, int nbatch, const int32_t* __restrict__ status,
+                  double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per_cfg = V * 81;
+  if (e >= per_cfg * nbatch) return;
+  const int b = (int)(e / per_cfg);
+  const int64_t r = e % per_cfg;
+  const int64_t blk = r / 9;
+  const int i = (int)(r % 9) / 3, j = (int)(r % 9) % 3;
+  double2 v = fronts[b * cfg_stride + sel_off[blk] + (int64_t)i * sel_ld[blk] + j];
+  if (status[b] != 0) v = make_double2(__builtin_nan(""), __builtin_nan(""));
+  out[e] = v;
+}
+
+// Fermionic drift per link (Eq. 8): K_a = tr(P B_a) + tr(Q F_a) with
+// F_a = c+ i lambda_a U, B_a = c- i U^{-1} lambda_a, P = Z_{x,x+nu}, Q = Z_{x+nu,x}.
+// Both traces collapse to K_a = tr(lambda_a M) with M = i (c- P U^{-1} + c+ U Q),
+// and the eight Gell-Mann traces are fixed linear combinations of M's entries.
+__global__ void __launch_bounds__(256)
+k_drift(const double2* __restrict__ sel, const double2* __restrict__ links,
+        const double2* __restrict__ linv, const double* __restrict__ muvals, LatticeDims dims,
+        int64_t V, int nbatch, double2* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= V * 4 * nbatch) return;
+  const int b = (int)(e / (V * 4));
+  const int64_t l = e % (V * 4);
+  const int64_t x = l / 4;
+  const int nu = (int)(l % 4);
+  int c[4];
+  dcoords(x, dims, c);
+  int cy[4] = {c[0], c[1], c[2], c[3]};
+  cy[nu] = (c[nu] + 1) % dims.L[nu];
+  const int64_t y = dsite(cy, dims);
+  const double mu = muvals[b];
+  const double cp = dcplus(c, nu, dims, exp(mu));
+  const double cm = dcminus(c, nu, dims, exp(-mu));
+  const double2* P = sel + ((int64_t)b * V + x) * 81 + (1 + nu) * 9;
+  const double2* Q = sel + ((int64_t)b * V + y) * 81 + (5 + nu) * 9;
+  const double2* U = links + ((int64_t)b * V * 4 + l) * 9;
+  const double2* Ui = linv + ((int64_t)b * V * 4 + l) * 9;
+  double2 Mm[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s1 = make_double2(0.0, 0.0), s2 = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        s1 = cfma(s1, P[i * 3 + k], Ui[k * 3 + j]);
+        s2 = cfma(s2, U[i * 3 + k], Q[k * 3 + j]);
+      }
+      const double2 t = cadd(cscale(s1, cm), cscale(s2, cp));
+      Mm[i * 3 + j] = make_double2(-t.y, t.x);  // multiply by i
+    }
+  const double2 m01 = Mm[1], m10 = Mm[3], m02 = Mm[2], m20 = Mm[6], m12 = Mm[5], m21 = Mm[7];
+  const double2 m00 = Mm[0], m11 = Mm[4], m22 = Mm[8];
+  const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
+  double2* o = out + e * 8;
+  // tr(lambda_a M) for the standard Gell-Mann matrices
+  o[0] = cadd(m01, m10);
+  o[1] = make_double2(-(m01.y - m10.y), m01.x - m10.x);  // i (M01 - M10)
+  o[2] = csub(m00, m11);
+  o[3] = cadd(m02, m20);
+  o[4] = make_double2(-(m02.y - m20.y), m02.x - m20.x);
+  o[5] = cadd(m12, m21);
+  o[6] = make_double2(-(m12.y - m21.y), m12.x - m21.x);
+  o[7] = cscale(make_double2(m00.x + m11.x - 2.0 * m22.x, m00.y + m11.y - 2.0 * m22.y), is3);
+}
+
+}  // namespace clsel

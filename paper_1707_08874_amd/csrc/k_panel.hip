@@ -1,0 +1,232 @@
+// Panel step of the frontal Gauss-Jordan sweep: pivot choice and pivot-block inverse.
+//
+// For the block of columns [k, k+nbk) of a front whose rows [k, p) are the pivot
+// candidates (row pivoting stays inside the supernode's own rows), this kernel
+//   phase 1: picks the nbk pivot rows by partial pivoting (largest modulus, lowest
+//            row on ties), running an in-place Gauss-Jordan elimination of the
+//            candidate rows over the panel columns in register groups of 16
+//            columns, with the remaining groups updated lazily in a workspace copy;
+//   phase 2: inverts Pi, the nbk x nbk block of the chosen rows in pivot order, by
+//            Gauss-Jordan elimination without further pivoting in LDS;
+//   and records the row permutation of the step and the equation held by each
+//   pivot row (needed to put the columns of the inverse back in natural order).
+// One work-group of 512 threads per (front, configuration).
+#include "desc.hpp"
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace clsel {
+
+constexpr int kPanelThreads = 512;
+constexpr int kGroup = 16;
+constexpr int kPiLd = kMaxNB + 1;
+
+template <int RPT>
+__global__ void __launch_bounds__(kPanelThreads)
+k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts, int64_t cfg_stride,
+        double2* __restrict__ ws, int64_t ws_stride, int32_t* __restrict__ iws, int64_t iws_stride,
+        int32_t* __restrict__ status) {
+  const PanelDesc d = descs[blockIdx.x];
+  const int b = blockIdx.y;
+  const int tid = threadIdx.x;
+  const double2* X = fronts + b * cfg_stride + d.x_off;
+  double2* PW = ws + b * ws_stride + d.pw_off;
+  double2* Pinv = ws + b * ws_stride + d.pinv_off;
+  int32_t* IW = iws + b * iws_stride;
+  const int cand = d.p - d.k, nbk = d.nbk, ld = d.ld, k = d.k;
+
+  __shared__ double2 s_prow[kGroup];
+  __shared__ double s_rv[kPanelThreads / 64];
+  __shared__ int s_ri[kPanelThreads / 64];
+  __shared__ int s_piv[kMaxNB];
+  __shared__ int s_pivot;
+  __shared__ int s_flag;
+  __shared__ double2 s_buf[kMaxNB * kPiLd];
+  __shared__ int s_at[kMaxPivotRows];
+  __shared__ int s_pos[kMaxPivotRows];
+
+  for (int64_t e = tid; e < (int64_t)cand * nbk; e += kPanelThreads) {
+    const int i = (int)(e / nbk), c = (int)(e % nbk);
+    PW[e] = X[(int64_t)(k + i) * ld + k + c];
+  }
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+
+  bool used[RPT];
+  double2 cur[RPT][kGroup];
+#pragma unroll
+  for (int j = 0; j < RPT; ++j) used[j] = false;
+
+  // ---- phase 1: pivot choice
+  for (int g0 = 0; g0 < nbk; g0 += kGroup) {
+    const int gw = min(kGroup, nbk - g0);
+#pragma unroll
+    for (int j = 0; j < RPT; ++j) {
+      const int r = tid + j * kPanelThreads;
+#pragma unroll
+      for (int c = 0; c < kGroup; ++c)
+        cur[j][c] = (r < cand && !used[j] && c < gw) ? PW[(int64_t)r * nbk + g0 + c]
+                                                       : make_double2(0.0, 0.0);
+    }
+    for (int c = 0; c < gw; ++c) {
+      double best = -1.0;
+      int bi = 0x7fffffff;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = tid + j * kPanelThreads;
+        double2 v = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int cc = 0; cc < kGroup; ++cc)
+          if (cc == c) v = cur[j][cc];
+        double a = cabs2(v);
+        if (!(a == a)) a = -0.5;  // NaN ranks below every number but is still a valid row
+        if (r < cand && !used[j] && a > best) { best = a; bi = r; }
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double ov = __shfl_xor(best, off);
+        const int oi = __shfl_xor(bi, off);
+        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+      }
+      if ((tid & 63) == 0) { s_rv[tid >> 6] = best; s_ri[tid >> 6] = bi; }
+      __syncthreads();
+      if (tid == 0) {
+        double bb = s_rv[0];
+        int ii = s_ri[0];
+        for (int w = 1; w < kPanelThreads / 64; ++w)
+          if (s_rv[w] > bb || (s_rv[w] == bb && s_ri[w] < ii)) { bb = s_rv[w]; ii = s_ri[w]; }
+        if (ii < 0 || ii >= cand) { ii = 0; bb = -1.0; }  // keeps every index in range
+        s_pivot = ii;
+        s_piv[g0 + c] = ii;
+        if (!(bb > 0.0) || !isfinite(bb)) s_flag = 1;
+      }
+      __syncthreads();
+      const int pr = s_pivot;
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        if (tid + j * kPanelThreads == pr) {
+#pragma unroll
+          for (int cc = 0; cc < kGroup; ++cc) s_prow[cc] = cur[j][cc];
+          used[j] = true;
+        }
+      }
+      __syncthreads();
+      double2 dp = s_prow[c];
+      if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) dp = make_double2(1.0, 0.0);
+      const double2 invd = crecip(dp);
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = tid + j * kPanelThreads;
+        if (r < cand && !used[j]) {
+          double2 f = make_double2(0.0, 0.0);
+#pragma unroll
+          for (int cc = 0; cc < kGroup; ++cc)
+            if (cc == c) f = cur[j][cc];
+          const double2 fi = cmul(f, invd);
+#pragma unroll
+          for (int cc = 0; cc < kGroup; ++cc) {
+            if (cc == c) cur[j][cc] = make_double2(-fi.x, -fi.y);
+            else cur[j][cc] = cfms(cur[j][cc], fi, s_prow[cc]);
+          }
+        }
+      }
+    }
+    // lazy update of the later column groups of the still-unused rows:
+    // PW[r][cc] += sum_t W_r[t] * R[t][cc], R = group pivot rows at group start
+    const int rest0 = g0 + gw, nrest = nbk - rest0;
+    if (nrest > 0) {
+      for (int e = tid; e < gw * nrest; e += kPanelThreads) {
+        const int t = e / nrest, cc = e % nrest;
+        s_buf[t * kMaxNB + cc] = PW[(int64_t)s_piv[g0 + t] * nbk + rest0 + cc];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < RPT; ++j) {
+        const int r = tid + j * kPanelThreads;
+        if (r < cand && !used[j]) {
+          for (int cc = 0; cc < nrest; ++cc) {
+            double2 acc = PW[(int64_t)r * nbk + rest0 + cc];
+#pragma unroll
+            for (int t = 0; t < kGroup; ++t)
+              if (t < gw) acc = cfma(acc, cur[j][t], s_buf[t * kMaxNB + cc]);
+            PW[(int64_t)r * nbk + rest0 + cc] = acc;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // ---- phase 2: Pi^{-1} by Gauss-Jordan in LDS (rows already in pivot order)
+  __syncthreads();
+  for (int e = tid; e < nbk * nbk; e += kPanelThreads) {
+    const int t = e / nbk, c = e % nbk;
+    s_buf[t * kPiLd + c] = X[(int64_t)(k + s_piv[t]) * ld + k + c];
+  }
+  __syncthreads();
+  constexpr int kPer = (kMaxNB * kMaxNB + kPanelThreads - 1) / kPanelThreads;
+  for (int c = 0; c < nbk; ++c) {
+    double2 dp = s_buf[c * kPiLd + c];
+    if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) {
+      if (tid == 0) s_flag = 1;
+      dp = make_double2(1.0, 0.0);
+    }
+    const double2 invd = crecip(dp);
+    double2 nv[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kPanelThreads;
+      if (e < nbk * nbk) {
+        const int t = e / nbk, cc = e % nbk;
+        const double2 a = s_buf[t * kPiLd + cc];
+        if (t == c) {
+          nv[q] = (cc == c) ? invd : cmul(a, invd);
+        } else {
+          const double2 fi = cmul(s_buf[t * kPiLd + c], invd);
+          nv[q] = (cc == c) ? make_double2(-fi.x, -fi.y) : cfms(a, fi, s_buf[c * kPiLd + cc]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kPanelThreads;
+      if (e < nbk * nbk) s_buf[(e / nbk) * kPiLd + (e % nbk)] = nv[q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nbk * nbk; e += kPanelThreads)
+    Pinv[e] = s_buf[(e / nbk) * kPiLd + (e % nbk)];
+
+  // ---- pivot list, row map of this step, equation ids of the pivot rows
+  if (tid < nbk) IW[d.piv_off + tid] = k + s_piv[tid];
+  for (int i = tid; i < cand; i += kPanelThreads) { s_at[i] = i; s_pos[i] = i; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int t = 0; t < nbk; ++t) {  // move candidate s_piv[t] to position t
+      const int r = s_piv[t], pr = s_pos[r], rt = s_at[t];
+      s_at[pr] = rt; s_pos[rt] = pr;
+      s_at[t] = r;   s_pos[r] = t;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < d.H; i += kPanelThreads)
+    IW[d.rmap_off + i] = (i >= k && i < d.p) ? k + s_at[i - k] : i;
+  int32_t* rowid = IW + d.rowid_off;
+  for (int i = tid; i < cand; i += kPanelThreads) s_pos[i] = rowid[k + s_at[i]];
+  __syncthreads();
+  for (int i = tid; i < cand; i += kPanelThreads) rowid[k + i] = s_pos[i];
+  if (tid == 0 && s_flag) atomicMin(&status[b], kStatusSingular);
+}
+
+void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs, const double2* fronts,
+                  int64_t cfg_stride, double2* ws, int64_t ws_stride, int32_t* iws,
+                  int64_t iws_stride, int32_t* status) {
+  switch (rpt) {
+    case 1: hipLaunchKernelGGL(k_panel<1>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status); break;
+    case 2: hipLaunchKernelGGL(k_panel<2>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status); break;
+    default: hipLaunchKernelGGL(k_panel<3>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status); break;
+  }
+}
+
+}  // namespace clsel

@@ -1,0 +1,40 @@
+// Kernel entry points and launch helpers of the HIP library.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "desc.hpp"
+#include "device.hpp"
+
+namespace clsel {
+
+constexpr int kMaxNB = 64;            // widest Gauss-Jordan block
+constexpr int kMaxPivotRows = 1536;   // pivot rows per supernode the panel kernel can hold
+constexpr int32_t kStatusSingular = -4;
+constexpr int32_t kStatusNonFinite = -5;
+
+__global__ void k_link_inverse(const double2* links, double2* linv, int64_t links_per_cfg,
+                               int nbatch, int32_t* status);
+__global__ void k_assemble(const AsmDesc* descs, int ndesc, double2* fronts, int64_t cfg_stride,
+                           const int32_t* front_sites, const int32_t* inv_maps,
+                           const double2* links, const double2* linv, int64_t link_cfg_stride,
+                           const double* mvals, const double* muvals, LatticeDims dims,
+                           int32_t* iws, int64_t iws_stride);
+__global__ void k_gather_zss(const GatherDesc* descs, int ndesc, double2* fronts,
+                             int64_t cfg_stride, const int32_t* rel_maps);
+__global__ void k_gather_selected(const double2* fronts, int64_t cfg_stride,
+                                  const int64_t* sel_off, const int32_t* sel_ld, int64_t V,
+                                  int nbatch, const int32_t* status, double2* out);
+__global__ void k_drift(const double2* sel, const double2* links, const double2* linv,
+                        const double* muvals, LatticeDims dims, int64_t V, int nbatch,
+                        double2* out);
+
+void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs,
+                  const double2* fronts, int64_t cfg_stride, double2* ws, int64_t ws_stride,
+                  int32_t* iws, int64_t iws_stride, int32_t* status);
+void launch_gemm(dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc, double2* fronts,
+                 int64_t cfg_stride, int64_t pool_elems, double2* ws, int64_t ws_stride,
+                 const int32_t* iws, int64_t iws_stride);
+
+}  // namespace clsel

@@ -1,0 +1,847 @@
+// Host runtime and C ABI: plans, batches, launch schedules, HIP-graph replay.
+//
+// A batch owns, per configuration, two front pools (the frontal Gauss-Jordan sweep
+// ping-pongs between them; the selected-inverse front of a supernode lands in the
+// pool its factorised front does not occupy), a complex and an int workspace, the
+// links, their inverses and the gathered selected blocks. All launch descriptors
+// are built once at batch creation from the immutable plan; a numeric call only
+// walks the precomputed launch list.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/clsel.h"
+#include "desc.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct cl_plan_s {
+  clsel::Plan P;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(CL_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+enum LaunchKind { kAsm = 1, kPanel, kGemm, kZss };
+
+struct Launch {
+  int kind;
+  size_t desc_off;   // byte offset into the device descriptor blob
+  int count;         // descriptors
+  int64_t gridx;
+  int rpt;           // panel rows per thread
+  double flops = 0;  // per configuration: 8*M*N*K summed over the GEMM problems
+};
+
+struct Layout {
+  int64_t cfg_stride = 0;   // 2 * pool_elems
+  int64_t ws_elems = 0;     // complex workspace per config
+  int64_t iws_elems = 0;    // int workspace per config
+  int64_t links_elems = 0;  // V*4*9
+  int64_t sel_elems = 0;    // V*81
+  std::vector<char> blob;
+  std::vector<Launch> factor, selinv;
+};
+
+size_t blob_push(std::vector<char>& blob, const void* p, size_t n) {
+  size_t off = (blob.size() + 255) & ~size_t(255);
+  blob.resize(off + n);
+  std::memcpy(blob.data() + off, p, n);
+  return off;
+}
+
+inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+void build_layout(const clsel::Plan& P, Layout& L) {
+  const int64_t pool = P.pool_elems;
+  const int nb = P.opt.nb;
+  L.cfg_stride = 2 * pool;
+  L.links_elems = P.V * 36;
+  L.sel_elems = P.V * 81;
+  // persistent int region: row ids of every front's pivot rows
+  std::vector<int64_t> rowid_base(P.fronts.size());
+  int64_t acc = 0;
+  for (size_t f = 0; f < P.fronts.size(); ++f) { rowid_base[f] = acc; acc += P.fronts[f].p; }
+  const int64_t istep0 = (acc + 63) & ~int64_t(63);
+  int64_t ws_max = 0, iws_max = istep0;
+
+  for (size_t lev = 0; lev < P.levels.size(); ++lev) {
+    const std::vector<int>& fl = P.levels[lev];
+    // assembly
+    std::vector<clsel::AsmDesc> ad;
+    int64_t blk = 0;
+    for (int f : fl) {
+      const clsel::Front& fr = P.fronts[f];
+      clsel::AsmDesc d{};
+      d.off = fr.off;  // pool 0
+      d.site_off = fr.site_off;
+      d.blk_start = blk;
+      blk += cdiv64((int64_t)fr.H * fr.H, 256);
+      d.H = fr.H; d.p = fr.p; d.ld = fr.ld; d.nchild = fr.nchild;
+      for (int c = 0; c < fr.nchild; ++c) {
+        const clsel::Front& ch = P.fronts[fr.child[c]];
+        d.inv_off[c] = fr.inv_off[c];
+        d.child_off[c] = ch.fbuf * pool + ch.off;
+        d.child_p[c] = ch.p;
+        d.child_ld[c] = ch.ld;
+      }
+      d.rowid_off = rowid_base[f];
+      ad.push_back(d);
+    }
+    L.factor.push_back({kAsm, blob_push(L.blob, ad.data(), ad.size() * sizeof(ad[0])),
+                        (int)ad.size(), blk, 0});
+    // Gauss-Jordan block steps
+    int steps = 0;
+    for (int f : fl) steps = std::max(steps, P.fronts[f].nsteps);
+    for (int q = 0; q < steps; ++q) {
+      std::vector<clsel::PanelDesc> pd;
+      std::vector<clsel::GemmDesc> g1, g2;
+      int64_t wso = 0, iwo = istep0, t1 = 0, t2 = 0;
+      int rpt = 1;
+      for (int f : fl) {
+        const clsel::Front& fr = P.fronts[f];
+        if (q >= fr.nsteps) continue;
+        const int k = q * nb, nbk = std::min(nb, fr.p - k), cand = fr.p - k;
+        rpt = std::max(rpt, (int)cdiv64(cand, 512));
+        clsel::PanelDesc p{};
+        p.x_off = (q % 2) * pool + fr.off;
+        p.pw_off = wso; wso += (int64_t)cand * nbk;
+        p.pinv_off = wso; wso += (int64_t)nbk * nbk;
+        const int64_t rt_off = wso; wso += (int64_t)nbk * fr.H;
+        wso = (wso + 15) & ~int64_t(15);
+        p.piv_off = iwo; iwo += nbk;
+        p.rmap_off = iwo; iwo += fr.H;
+        iwo = (iwo + 63) & ~int64_t(63);
+        p.rowid_off = rowid_base[f];
+        p.H = fr.H; p.p = fr.p; p.ld = fr.ld; p.k = k; p.nbk = nbk;
+        pd.push_back(p);
+        clsel::GemmDesc a{};
+        a.mode = 1; a.M = nbk; a.N = fr.H; a.K = nbk;
+        a.tiles_n = (int)cdiv64(fr.H, 64);
+        a.tile_start = t1; t1 += a.tiles_n;
+        a.k = k; a.nbk = nbk; a.p = fr.p; a.ld = fr.ld; a.last = 0;
+        a.x_off = p.x_off; a.y_off = ((q + 1) % 2) * pool + fr.off;
+        a.rt_off = rt_off; a.pinv_off = p.pinv_off; a.piv_off = p.piv_off;
+        a.rmap_off = p.rmap_off; a.rowid_off = p.rowid_off;
+        g1.push_back(a);
+        clsel::GemmDesc u = a;
+        u.mode = 2; u.M = fr.H; u.N = fr.H; u.K = nbk;
+        u.tiles_n = (int)cdiv64(fr.H, 64);
+        u.tile_start = t2; t2 += cdiv64(fr.H, 64) * u.tiles_n;
+        u.last = (q == fr.nsteps - 1) ? 1 : 0;
+        g2.push_back(u);
+      }
+      ws_max = std::max(ws_max, wso);
+      iws_max = std::max(iws_max, iwo);
+      L.factor.push_back({kPanel, blob_push(L.blob, pd.data(), pd.size() * sizeof(pd[0])),
+                          (int)pd.size(), (int64_t)pd.size(), rpt});
+      L.factor.push_back({kGemm, blob_push(L.blob, g1.data(), g1.size() * sizeof(g1[0])),
+                          (int)g1.size(), t1, 0});
+      L.factor.push_back({kGemm, blob_push(L.blob, g2.data(), g2.size() * sizeof(g2[0])),
+                          (int)g2.size(), t2, 0});
+    }
+  }
+
+  // selected inversion, root level first
+  for (int lev = (int)P.levels.size() - 1; lev >= 0; --lev) {
+    std::vector<clsel::GatherDesc> gd;
+    std::vector<clsel::GemmDesc> ga, gb;
+    int64_t blk = 0, ta = 0, tb = 0;
+    for (int f : P.levels[lev]) {
+      const clsel::Front& fr = P.fronts[f];
+      if (fr.s == 0) continue;  // the root's factorised front is its own inverse
+      const clsel::Front& par = P.fronts[fr.parent];
+      clsel::GatherDesc g{};
+      g.z_off = fr.zbuf * pool + fr.off;
+      g.par_off = par.zbuf * pool + par.off;
+      g.rel_off = fr.rel_off;
+      g.blk_start = blk;
+      blk += cdiv64((int64_t)fr.s * fr.s, 256);
+      g.p = fr.p; g.s = fr.s; g.ld = fr.ld; g.par_ld = par.ld;
+      gd.push_back(g);
+      const int zp = fr.zbuf, fp = fr.fbuf, ld = fr.ld;
+      const int64_t o = fr.off, p = fr.p;
+      // Z_SJ = Z_SS * (-L^)   (F[SJ] holds -A_SJ A_JJ^{-1})
+      clsel::GemmDesc sj{};
+      sj.mode = 0; sj.M = fr.s; sj.N = fr.p; sj.K = fr.s;
+      sj.a_pool = zp; sj.a_off = o + p * ld + p; sj.lda = ld;
+      sj.b_pool = fp; sj.b_off = o + p * ld; sj.ldb = ld;
+      sj.c_pool = zp; sj.c_off = o + p * ld; sj.ldc = ld;
+      sj.alpha = 1.0; sj.has_c0 = 0;
+      sj.tiles_n = (int)cdiv64(sj.N, 64);
+      sj.tile_start = ta; ta += cdiv64(sj.M, 64) * sj.tiles_n;
+      ga.push_back(sj);
+      // Z_JS = -U^ * Z_SS   (F[JS] holds A_JJ^{-1} A_JS)
+      clsel::GemmDesc js{};
+      js.mode = 0; js.M = fr.p; js.N = fr.s; js.K = fr.s;
+      js.a_pool = fp; js.a_off = o + p; js.lda = ld;
+      js.b_pool = zp; js.b_off = o + p * ld + p; js.ldb = ld;
+      js.c_pool = zp; js.c_off = o + p; js.ldc = ld;
+      js.alpha = -1.0; js.has_c0 = 0;
+      js.tiles_n = (int)cdiv64(js.N, 64);
+      js.tile_start = ta; ta += cdiv64(js.M, 64) * js.tiles_n;
+      ga.push_back(js);
+      // Z_JJ = A_JJ^{-1} - U^ * Z_SJ
+      clsel::GemmDesc jj{};
+      jj.mode = 0; jj.M = fr.p; jj.N = fr.p; jj.K = fr.s;
+      jj.a_pool = fp; jj.a_off = o + p; jj.lda = ld;
+      jj.b_pool = zp; jj.b_off = o + p * ld; jj.ldb = ld;
+      jj.c_pool = zp; jj.c_off = o; jj.ldc = ld;
+      jj.c0_pool = fp; jj.c0_off = o; jj.ldc0 = ld;
+      jj.alpha = -1.0; jj.has_c0 = 1;
+      jj.tiles_n = (int)cdiv64(jj.N, 64);
+      jj.tile_start = tb; tb += cdiv64(jj.M, 64) * jj.tiles_n;
+      gb.push_back(jj);
+    }
+    if (gd.empty()) continue;
+    L.selinv.push_back({kZss, blob_push(L.blob, gd.data(), gd.size() * sizeof(gd[0])),
+                        (int)gd.size(), blk, 0});
+    L.selinv.push_back({kGemm, blob_push(L.blob, ga.data(), ga.size() * sizeof(ga[0])),
+                        (int)ga.size(), ta, 0});
+    L.selinv.push_back({kGemm, blob_push(L.blob, gb.data(), gb.size() * sizeof(gb[0])),
+                        (int)gb.size(), tb, 0});
+  }
+  L.ws_elems = std::max<int64_t>(ws_max, 16);
+  L.iws_elems = iws_max;
+  for (std::vector<Launch>* ls : {&L.factor, &L.selinv})
+    for (Launch& l : *ls) {
+      if (l.kind != kGemm) continue;
+      const clsel::GemmDesc* d = (const clsel::GemmDesc*)(L.blob.data() + l.desc_off);
+      for (int i = 0; i < l.count; ++i) l.flops += 8.0 * d[i].M * d[i].N * d[i].K;
+    }
+}
+
+// Checks on the host that every index a kernel can form from the launch tables stays
+// inside its buffer, so that a bad plan or layout is an error here and never an
+// out-of-bounds access on the device.
+bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
+  const int64_t pool = P.pool_elems, two = 2 * pool;
+  auto bad = [&](const char* what, int64_t a, int64_t lim) {
+    why = std::string(what) + ": " + std::to_string(a) + " > " + std::to_string(lim);
+    return false;
+  };
+#define REQ(cond, what, a, lim) do { if (!(cond)) return bad(what, (a), (lim)); } while (0)
+  int64_t rowid_total = 0;
+  for (const clsel::Front& f : P.fronts) rowid_total += f.p;
+  for (const Launch& l : L.factor) {
+    const char* base = L.blob.data() + l.desc_off;
+    if (l.kind == kAsm) {
+      const clsel::AsmDesc* d = (const clsel::AsmDesc*)base;
+      int64_t blk = 0;
+      for (int i = 0; i < l.count; ++i) {
+        REQ(d[i].blk_start == blk, "asm block start", d[i].blk_start, blk);
+        blk += cdiv64((int64_t)d[i].H * d[i].H, 256);
+        REQ(d[i].off + (int64_t)d[i].H * d[i].ld <= pool, "asm front", d[i].off, pool);
+        REQ(d[i].site_off + d[i].H / 3 <= (int64_t)P.front_sites.size(), "asm sites", d[i].site_off, 0);
+        REQ(d[i].rowid_off + d[i].p <= rowid_total, "asm rowid", d[i].rowid_off, rowid_total);
+        for (int c = 0; c < d[i].nchild; ++c) {
+          REQ(d[i].inv_off[c] + d[i].H <= (int64_t)P.inv_maps.size(), "asm inv map", d[i].inv_off[c], 0);
+          int64_t cs = 0;
+          for (int64_t r = 0; r < d[i].H; ++r) cs = std::max<int64_t>(cs, P.inv_maps[d[i].inv_off[c] + r] + 1);
+          REQ(d[i].child_off[c] + (int64_t)(d[i].child_p[c] + cs - 1) * d[i].child_ld[c] + d[i].child_p[c] + cs <= two,
+              "asm child front", d[i].child_off[c], two);
+        }
+      }
+      REQ(blk == l.gridx, "asm grid", blk, l.gridx);
+    } else if (l.kind == kPanel) {
+      const clsel::PanelDesc* d = (const clsel::PanelDesc*)base;
+      REQ(l.rpt >= 1 && l.rpt <= 3, "panel rpt", l.rpt, 3);
+      for (int i = 0; i < l.count; ++i) {
+        const int cand = d[i].p - d[i].k;
+        REQ(cand >= d[i].nbk && d[i].nbk >= 1 && d[i].nbk <= clsel::kMaxNB, "panel nbk", d[i].nbk, cand);
+        REQ(cand <= 512 * l.rpt && cand <= clsel::kMaxPivotRows, "panel candidates", cand, 512 * l.rpt);
+        REQ(d[i].x_off + (int64_t)d[i].H * d[i].ld <= two, "panel front", d[i].x_off, two);
+        REQ(d[i].pw_off + (int64_t)cand * d[i].nbk <= L.ws_elems, "panel pw", d[i].pw_off, L.ws_elems);
+        REQ(d[i].pinv_off + (int64_t)d[i].nbk * d[i].nbk <= L.ws_elems, "panel pinv", d[i].pinv_off, L.ws_elems);
+        REQ(d[i].piv_off + d[i].nbk <= L.iws_elems, "panel piv", d[i].piv_off, L.iws_elems);
+        REQ(d[i].rmap_off + d[i].H <= L.iws_elems, "panel rmap", d[i].rmap_off, L.iws_elems);
+        REQ(d[i].rowid_off + d[i].p <= rowid_total, "panel rowid", d[i].rowid_off, rowid_total);
+      }
+    }
+  }
+  auto check_gemms = [&](const std::vector<Launch>& ls) -> bool {
+    for (const Launch& l : ls) {
+      if (l.kind != kGemm) continue;
+      const clsel::GemmDesc* d = (const clsel::GemmDesc*)(L.blob.data() + l.desc_off);
+      int64_t t = 0;
+      for (int i = 0; i < l.count; ++i) {
+        const clsel::GemmDesc& g = d[i];
+        REQ(g.tile_start == t, "gemm tile start", g.tile_start, t);
+        t += cdiv64(g.M, 64) * g.tiles_n;
+        REQ(g.tiles_n == cdiv64(g.N, 64), "gemm tiles_n", g.tiles_n, cdiv64(g.N, 64));
+        if (g.mode == 0) {
+          auto lim = [&](int pool_id) { return pool_id == clsel::kPoolWs ? L.ws_elems : pool; };
+          REQ(g.a_off + (int64_t)(g.M - 1) * g.lda + g.K <= lim(g.a_pool), "gemm A", g.a_off, lim(g.a_pool));
+          REQ(g.b_off + (int64_t)(g.K - 1) * g.ldb + g.N <= lim(g.b_pool), "gemm B", g.b_off, lim(g.b_pool));
+          REQ(g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N <= lim(g.c_pool), "gemm C", g.c_off, lim(g.c_pool));
+          if (g.has_c0) REQ(g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N <= lim(g.c0_pool), "gemm C0", g.c0_off, 0);
+        } else {
+          const int H = g.mode == 1 ? g.N : g.M;
+          REQ(g.x_off + (int64_t)H * g.ld <= two && g.y_off + (int64_t)H * g.ld <= two, "gemm front", g.x_off, two);
+          REQ(g.rt_off + (int64_t)g.nbk * H <= L.ws_elems, "gemm Rt", g.rt_off, L.ws_elems);
+          REQ(g.pinv_off + (int64_t)g.nbk * g.nbk <= L.ws_elems, "gemm pinv", g.pinv_off, L.ws_elems);
+          REQ(g.piv_off + g.nbk <= L.iws_elems && g.rmap_off + H <= L.iws_elems, "gemm maps", g.rmap_off, L.iws_elems);
+          REQ(g.K == g.nbk && g.k + g.nbk <= g.p && g.p <= H, "gemm step", g.k, g.p);
+        }
+      }
+      REQ(t == l.gridx, "gemm grid", t, l.gridx);
+    }
+    return true;
+  };
+  if (!check_gemms(L.factor) || !check_gemms(L.selinv)) return false;
+  for (const Launch& l : L.selinv) {
+    if (l.kind != kZss) continue;
+    const clsel::GatherDesc* d = (const clsel::GatherDesc*)(L.blob.data() + l.desc_off);
+    for (int i = 0; i < l.count; ++i) {
+      const int64_t H = d[i].p + d[i].s;
+      REQ(d[i].z_off + H * d[i].ld <= two, "gather front", d[i].z_off, two);
+      REQ(d[i].rel_off + d[i].s <= (int64_t)P.rel_maps.size(), "gather rel", d[i].rel_off, 0);
+      int64_t mx = 0;
+      for (int a = 0; a < d[i].s; ++a) mx = std::max<int64_t>(mx, P.rel_maps[d[i].rel_off + a]);
+      REQ(d[i].par_off + mx * d[i].par_ld + mx < two, "gather parent", d[i].par_off, two);
+    }
+  }
+  for (size_t i = 0; i < P.sel_off.size(); ++i)
+    REQ(P.sel_off[i] + 2 * (int64_t)P.sel_ld[i] + 2 < two && P.sel_off[i] >= 0, "selected offset", P.sel_off[i], two);
+#undef REQ
+  return true;
+}
+
+size_t layout_bytes(const clsel::Plan& P, const Layout& L, int64_t B) {
+  size_t b = 0;
+  b += (size_t)B * L.cfg_stride * 16;        // fronts
+  b += (size_t)B * L.ws_elems * 16;          // complex workspace
+  b += (size_t)B * L.iws_elems * 4;          // int workspace
+  b += (size_t)B * L.links_elems * 16 * 2;   // links + inverses
+  b += (size_t)B * L.sel_elems * 16;         // selected blocks
+  b += (size_t)B * (16 + 4);                 // params + status
+  b += L.blob.size();
+  b += P.front_sites.size() * 4 + P.inv_maps.size() * 4 + P.rel_maps.size() * 4;
+  b += P.sel_off.size() * 8 + P.sel_ld.size() * 4;
+  return b;
+}
+
+__global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+struct cl_batch_s {
+  cl_plan plan = nullptr;
+  Layout L;
+  int cap = 0, active = 0;
+  int device = 0;
+  hipStream_t user = nullptr, st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_param = nullptr;
+  double2* fronts = nullptr;
+  double2* ws = nullptr;
+  int32_t* iws = nullptr;
+  double2* links = nullptr;
+  double2* linv = nullptr;
+  double2* sel = nullptr;
+  double* params = nullptr;       // device: m[cap], mu[cap]
+  double* params_host = nullptr;  // pinned staging
+  int32_t* status = nullptr;
+  char* dblob = nullptr;
+  int32_t* d_front_sites = nullptr;
+  int32_t* d_inv = nullptr;
+  int32_t* d_rel = nullptr;
+  int64_t* d_sel_off = nullptr;
+  int32_t* d_sel_ld = nullptr;
+  int state = 0;  // 0 created, 1 factored, 2 inverted
+  bool use_graph = false;
+  hipGraphExec_t gexec = nullptr;
+  const void* g_links = nullptr;
+  void* g_sel = nullptr;
+  void* g_drift = nullptr;
+  int g_active = 0;
+  // optional per-launch timing of the GEMM kernels (HIP events on the batch stream)
+  bool prof = false;
+  std::vector<hipEvent_t> prof_ev;   // pairs, recorded around each GEMM launch
+  std::vector<double> prof_flops;    // algorithmic flops of each timed launch
+  size_t prof_used = 0;
+  double prof_ms = 0, prof_flop_total = 0;
+  int64_t prof_launches = 0;
+};
+
+namespace {
+
+template <class T>
+int dalloc(T** p, size_t n) {
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return fail(e == hipErrorOutOfMemory ? CL_ENOMEM : CL_EHIP,
+                std::string("hipMalloc: ") + hipGetErrorString(e));
+  }
+  return 0;
+}
+
+template <class T>
+int upload(T** p, const std::vector<T>& v) {
+  int rc = dalloc(p, v.size());
+  if (rc) return rc;
+  if (!v.empty()) HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return 0;
+}
+
+clsel::LatticeDims ldims(const clsel::Plan& P) {
+  clsel::LatticeDims d;
+  for (int k = 0; k < 4; ++k) d.L[k] = P.dims[k];
+  return d;
+}
+
+int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active;
+  for (const Launch& l : ls) {
+    if (l.gridx <= 0) continue;
+    const dim3 grid((unsigned)l.gridx, (unsigned)B);
+    const char* dp = b->dblob + l.desc_off;
+    switch (l.kind) {
+      case kAsm:
+        hipLaunchKernelGGL(clsel::k_assemble, grid, dim3(256), 0, b->st,
+                           (const clsel::AsmDesc*)dp, l.count, b->fronts, b->L.cfg_stride,
+                           b->d_front_sites, b->d_inv, b->links, b->linv, b->L.links_elems,
+                           b->params, b->params + b->cap, ldims(P), b->iws, b->L.iws_elems);
+        break;
+      case kPanel:
+        clsel::launch_panel(l.rpt, grid, b->st, (const clsel::PanelDesc*)dp, b->fronts,
+                            b->L.cfg_stride, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
+                            b->status);
+        break;
+      case kGemm: {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (b->prof) {
+          if (b->prof_used + 2 > b->prof_ev.size()) {
+            for (int k = 0; k < 64; ++k) {
+              hipEvent_t e;
+              HIPCHK(hipEventCreate(&e));
+              b->prof_ev.push_back(e);
+            }
+          }
+          e0 = b->prof_ev[b->prof_used];
+          e1 = b->prof_ev[b->prof_used + 1];
+          b->prof_used += 2;
+          b->prof_flops.push_back(l.flops * B);
+          HIPCHK(hipEventRecord(e0, b->st));
+        }
+        clsel::launch_gemm(grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
+                           b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws,
+                           b->L.iws_elems);
+        if (b->prof) HIPCHK(hipEventRecord(e1, b->st));
+        break;
+      }
+      case kZss:
+        hipLaunchKernelGGL(clsel::k_gather_zss, grid, dim3(256), 0, b->st,
+                           (const clsel::GatherDesc*)dp, l.count, b->fronts, b->L.cfg_stride,
+                           b->d_rel);
+        break;
+    }
+    HIPCHK(hipGetLastError());
+  }
+  return 0;
+}
+
+int enqueue_factor(cl_batch b, const void* links_dev, bool capturing) {
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active;
+  HIPCHK(hipMemcpyAsync(b->params, b->params_host, sizeof(double) * 2 * b->cap,
+                        hipMemcpyHostToDevice, b->st));
+  // marks the pinned staging buffer reusable; under capture it is recorded after the launch
+  if (!capturing) HIPCHK(hipEventRecord(b->ev_param, b->st));
+  HIPCHK(hipMemcpyAsync(b->links, links_dev, sizeof(double2) * b->L.links_elems * B,
+                        hipMemcpyDeviceToDevice, b->st));
+  hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, b->st, b->status, B, 0);
+  HIPCHK(hipGetLastError());
+  const int64_t nl = P.V * 4 * (int64_t)B;
+  hipLaunchKernelGGL(clsel::k_link_inverse, dim3((unsigned)cdiv64(nl, 256)), dim3(256), 0, b->st,
+                     b->links, b->linv, P.V * 4, B, b->status);
+  HIPCHK(hipGetLastError());
+  return enqueue_launches(b, b->L.factor);
+}
+
+int enqueue_selinv(cl_batch b) {
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active;
+  int rc = enqueue_launches(b, b->L.selinv);
+  if (rc) return rc;
+  const int64_t n = P.V * 81 * (int64_t)B;
+  hipLaunchKernelGGL(clsel::k_gather_selected, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0,
+                     b->st, b->fronts, b->L.cfg_stride, b->d_sel_off, b->d_sel_ld, P.V, B,
+                     b->status, b->sel);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int enqueue_selected(cl_batch b, void* out) {
+  HIPCHK(hipMemcpyAsync(out, b->sel, sizeof(double2) * b->L.sel_elems * b->active,
+                        hipMemcpyDeviceToDevice, b->st));
+  return 0;
+}
+
+int enqueue_drift(cl_batch b, void* out) {
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active;
+  const int64_t n = P.V * 4 * (int64_t)B;
+  hipLaunchKernelGGL(clsel::k_drift, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, b->st, b->sel,
+                     b->links, b->linv, b->params + b->cap, ldims(P), P.V, B, (double2*)out);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int begin(cl_batch b) {
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipEventRecord(b->ev_in, b->user));
+  HIPCHK(hipStreamWaitEvent(b->st, b->ev_in, 0));
+  return 0;
+}
+
+int end(cl_batch b) {
+  HIPCHK(hipEventRecord(b->ev_out, b->st));
+  HIPCHK(hipStreamWaitEvent(b->user, b->ev_out, 0));
+  return 0;
+}
+
+int stage_params(cl_batch b, const double* m, const double* mu) {
+  // the previous call's parameter upload must have left the pinned buffer
+  HIPCHK(hipEventSynchronize(b->ev_param));
+  for (int i = 0; i < b->active; ++i) {
+    b->params_host[i] = m[i];
+    b->params_host[b->cap + i] = mu[i];
+  }
+  return 0;
+}
+
+void free_batch(cl_batch b) {
+  if (!b) return;
+  if (b->gexec) hipGraphExecDestroy(b->gexec);
+  hipFree(b->fronts); hipFree(b->ws); hipFree(b->iws); hipFree(b->links); hipFree(b->linv);
+  hipFree(b->sel); hipFree(b->params); hipFree(b->status); hipFree(b->dblob);
+  hipFree(b->d_front_sites); hipFree(b->d_inv); hipFree(b->d_rel); hipFree(b->d_sel_off);
+  hipFree(b->d_sel_ld);
+  if (b->params_host) hipHostFree(b->params_host);
+  for (hipEvent_t e : b->prof_ev) hipEventDestroy(e);
+  if (b->ev_in) hipEventDestroy(b->ev_in);
+  if (b->ev_out) hipEventDestroy(b->ev_out);
+  if (b->ev_param) hipEventDestroy(b->ev_param);
+  if (b->st) hipStreamDestroy(b->st);
+  delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cl_strerror(int code) {
+  switch (code) {
+    case CL_OK: return "ok";
+    case CL_EINVAL: return "invalid argument";
+    case CL_ENOMEM: return "out of memory";
+    case CL_EORDER: return "call out of order";
+    case CL_ESINGULAR: return "singular pivot block";
+    case CL_ENONFINITE: return "non-finite or singular link";
+    case CL_EHIP: return "HIP runtime error";
+    case CL_ENODEV: return "no usable GPU";
+    default: return "unknown error";
+  }
+}
+
+const char* cl_last_error(void) { return g_err.c_str(); }
+
+int cl_symbolic_ex(const int32_t dims[4], const cl_plan_opts* opts, cl_plan* out) {
+  if (!dims || !out) return fail(CL_EINVAL, "null pointer");
+  clsel::PlanOptions o;
+  if (opts) {
+    if (opts->leaf_sites > 0) o.leaf_sites = opts->leaf_sites;
+    if (opts->max_pivot_rows > 0) o.max_pivot_rows = opts->max_pivot_rows;
+    if (opts->nb > 0) o.nb = opts->nb;
+  }
+  if (o.max_pivot_rows > clsel::kMaxPivotRows || o.max_pivot_rows < 3)
+    return fail(CL_EINVAL, "max_pivot_rows must be in [3, 1536]");
+  if (o.nb > clsel::kMaxNB) return fail(CL_EINVAL, "nb must be in [1, 64]");
+  cl_plan p = new (std::nothrow) cl_plan_s;
+  if (!p) return fail(CL_ENOMEM, "plan allocation");
+  std::string err;
+  if (clsel::build_plan(dims, o, p->P, err) != 0) {
+    delete p;
+    return fail(CL_EINVAL, err);
+  }
+  *out = p;
+  return 0;
+}
+
+int cl_symbolic(const int32_t dims[4], cl_plan* out) { return cl_symbolic_ex(dims, nullptr, out); }
+
+int cl_plan_info(cl_plan plan, cl_plan_info_t* o) {
+  if (!plan || !o) return fail(CL_EINVAL, "null pointer");
+  const clsel::Plan& P = plan->P;
+  for (int k = 0; k < 4; ++k) o->dims[k] = P.dims[k];
+  o->volume = P.V;
+  o->n = P.N;
+  o->nfronts = (int32_t)P.fronts.size();
+  o->nlevels = (int32_t)P.levels.size();
+  o->max_steps = P.max_steps;
+  o->max_front_rows = P.max_H;
+  o->max_pivot_rows = P.max_p;
+  o->pool_elems = P.pool_elems;
+  o->flops_factor = P.flops_factor_exec;
+  o->flops_selinv = P.flops_selinv_exec;
+  o->flops_factor_alg = P.flops_factor_alg;
+  o->flops_selinv_alg = P.flops_selinv_alg;
+  o->flops_dense_inverse = P.flops_dense_inverse;
+  return 0;
+}
+
+size_t cl_plan_bytes(cl_plan plan, int32_t batch) {
+  if (!plan || batch < 1) return 0;
+  Layout L;
+  build_layout(plan->P, L);
+  std::string why;
+  if (!validate_layout(plan->P, L, why)) { g_err = why; return 0; }
+  return layout_bytes(plan->P, L, batch);
+}
+
+int cl_plan_export(cl_plan plan, int32_t what, void* dst, size_t* nbytes) {
+  if (!plan || !nbytes) return fail(CL_EINVAL, "null pointer");
+  const clsel::Plan& P = plan->P;
+  std::vector<int64_t> rows;
+  const void* src = nullptr;
+  size_t n = 0;
+  switch (what) {
+    case 0:
+      for (const clsel::Front& f : P.fronts) {
+        const int64_t r[CL_FRONT_FIELDS] = {
+            f.id, f.parent, f.level, f.npiv, f.nstr, f.p, f.s, f.H, f.ld, f.off, f.site_off,
+            f.nchild, f.child[0], f.child[1], f.child[2], f.child[3], f.inv_off[0], f.inv_off[1],
+            f.inv_off[2], f.inv_off[3], f.rel_off, f.nsteps, f.fbuf, f.zbuf, 0, 0, 0, 0};
+        rows.insert(rows.end(), r, r + CL_FRONT_FIELDS);
+      }
+      src = rows.data(); n = rows.size() * 8; break;
+    case 1: src = P.front_sites.data(); n = P.front_sites.size() * 4; break;
+    case 2: src = P.inv_maps.data(); n = P.inv_maps.size() * 4; break;
+    case 3: src = P.rel_maps.data(); n = P.rel_maps.size() * 4; break;
+    case 4: src = P.sel_off.data(); n = P.sel_off.size() * 8; break;
+    case 5: src = P.order.data(); n = P.order.size() * 8; break;
+    default: return fail(CL_EINVAL, "unknown table");
+  }
+  if (dst) {
+    if (*nbytes < n) return fail(CL_EINVAL, "destination too small");
+    std::memcpy(dst, src, n);
+  }
+  *nbytes = n;
+  return 0;
+}
+
+void cl_plan_destroy(cl_plan plan) { delete plan; }
+
+int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out) {
+  if (!plan || !out || batch < 1 || batch > 65535) return fail(CL_EINVAL, "bad plan, batch or output");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(CL_ENODEV, "no GPU visible");
+  cl_batch b = new (std::nothrow) cl_batch_s;
+  if (!b) return fail(CL_ENOMEM, "batch allocation");
+  b->plan = plan;
+  b->cap = b->active = batch;
+  b->user = (hipStream_t)hip_stream;
+  const clsel::Plan& P = plan->P;
+  build_layout(P, b->L);
+  {
+    std::string why;
+    if (!validate_layout(P, b->L, why)) { delete b; return fail(CL_EINVAL, "launch table check failed: " + why); }
+  }
+  int rc = 0;
+#define TRY(x) do { rc = (x); if (rc) { free_batch(b); return rc; } } while (0)
+#define HTRY(x) do { hipError_t e_ = (x); if (e_ != hipSuccess) { free_batch(b); return fail(CL_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); } } while (0)
+  HTRY(hipGetDevice(&b->device));
+  HTRY(hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking));
+  HTRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+  HTRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+  HTRY(hipEventCreateWithFlags(&b->ev_param, hipEventDisableTiming));
+  HTRY(hipEventRecord(b->ev_param, b->st));
+  const int64_t B = batch;
+  TRY(dalloc(&b->fronts, (size_t)(B * b->L.cfg_stride)));
+  TRY(dalloc(&b->ws, (size_t)(B * b->L.ws_elems)));
+  TRY(dalloc(&b->iws, (size_t)(B * b->L.iws_elems)));
+  TRY(dalloc(&b->links, (size_t)(B * b->L.links_elems)));
+  TRY(dalloc(&b->linv, (size_t)(B * b->L.links_elems)));
+  TRY(dalloc(&b->sel, (size_t)(B * b->L.sel_elems)));
+  TRY(dalloc(&b->params, (size_t)(2 * B)));
+  TRY(dalloc(&b->status, (size_t)B));
+  {
+    hipError_t e = hipHostMalloc((void**)&b->params_host, sizeof(double) * 2 * B, hipHostMallocDefault);
+    if (e != hipSuccess) { b->params_host = nullptr; free_batch(b); return fail(CL_ENOMEM, "pinned staging"); }
+    std::memset(b->params_host, 0, sizeof(double) * 2 * B);
+  }
+  TRY(dalloc(&b->dblob, b->L.blob.size()));
+  HTRY(hipMemcpy(b->dblob, b->L.blob.data(), b->L.blob.size(), hipMemcpyHostToDevice));
+  TRY(upload(&b->d_front_sites, P.front_sites));
+  TRY(upload(&b->d_inv, P.inv_maps));
+  TRY(upload(&b->d_rel, P.rel_maps));
+  TRY(upload(&b->d_sel_off, P.sel_off));
+  TRY(upload(&b->d_sel_ld, P.sel_ld));
+  HTRY(hipMemset(b->status, 0, sizeof(int32_t) * B));
+#undef TRY
+#undef HTRY
+  *out = b;
+  return 0;
+}
+
+int cl_batch_set_active(cl_batch b, int32_t n) {
+  if (!b || n < 1 || n > b->cap) return fail(CL_EINVAL, "active count out of range");
+  if (n != b->active) { b->active = n; b->state = 0; }
+  return 0;
+}
+
+int cl_batch_use_graph(cl_batch b, int32_t enable) {
+  if (!b) return fail(CL_EINVAL, "null batch");
+  b->use_graph = enable != 0;
+  return 0;
+}
+
+int cl_factor(cl_batch b, const void* links_dev, const double* m_host, const double* mu_host) {
+  if (!b || !links_dev || !m_host || !mu_host) return fail(CL_EINVAL, "null argument");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  if ((rc = stage_params(b, m_host, mu_host))) return rc;
+  if ((rc = enqueue_factor(b, links_dev, false))) return rc;
+  b->state = 1;
+  return end(b);
+}
+
+int cl_selinv(cl_batch b) {
+  if (!b) return fail(CL_EINVAL, "null batch");
+  if (b->state < 1) return fail(CL_EORDER, "cl_selinv before cl_factor");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  if ((rc = enqueue_selinv(b))) return rc;
+  b->state = 2;
+  return end(b);
+}
+
+int cl_selected(cl_batch b, void* out) {
+  if (!b || !out) return fail(CL_EINVAL, "null argument");
+  if (b->state < 2) return fail(CL_EORDER, "cl_selected before cl_selinv");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  if ((rc = enqueue_selected(b, out))) return rc;
+  return end(b);
+}
+
+int cl_drift(cl_batch b, void* out) {
+  if (!b || !out) return fail(CL_EINVAL, "null argument");
+  if (b->state < 2) return fail(CL_EORDER, "cl_drift before cl_selinv");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  if ((rc = enqueue_drift(b, out))) return rc;
+  return end(b);
+}
+
+int cl_run(cl_batch b, const void* links_dev, const double* m_host, const double* mu_host,
+           void* sel_out, void* drift_out) {
+  if (!b || !links_dev || !m_host || !mu_host) return fail(CL_EINVAL, "null argument");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  if ((rc = stage_params(b, m_host, mu_host))) return rc;
+  if (!b->use_graph) {
+    if ((rc = enqueue_factor(b, links_dev, false))) return rc;
+    if ((rc = enqueue_selinv(b))) return rc;
+    if (sel_out && (rc = enqueue_selected(b, sel_out))) return rc;
+    if (drift_out && (rc = enqueue_drift(b, drift_out))) return rc;
+  } else {
+    if (!b->gexec || b->g_links != links_dev || b->g_sel != sel_out || b->g_drift != drift_out ||
+        b->g_active != b->active) {
+      if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+      HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_factor(b, links_dev, true);
+      if (!rc) rc = enqueue_selinv(b);
+      if (!rc && sel_out) rc = enqueue_selected(b, sel_out);
+      if (!rc && drift_out) rc = enqueue_drift(b, drift_out);
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamEndCapture(b->st, &graph);
+      if (rc) { if (graph) hipGraphDestroy(graph); return rc; }
+      if (e != hipSuccess) return fail(CL_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+      e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+      hipGraphDestroy(graph);
+      if (e != hipSuccess) { b->gexec = nullptr; return fail(CL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); }
+      b->g_links = links_dev; b->g_sel = sel_out; b->g_drift = drift_out; b->g_active = b->active;
+    }
+    HIPCHK(hipGraphLaunch(b->gexec, b->st));
+    HIPCHK(hipEventRecord(b->ev_param, b->st));
+  }
+  b->state = 2;
+  return end(b);
+}
+
+int cl_batch_profile(cl_batch b, int32_t enable) {
+  if (!b) return fail(CL_EINVAL, "null batch");
+  if (enable && b->use_graph) return fail(CL_EINVAL, "profiling needs the eager path");
+  b->prof = enable != 0;
+  return 0;
+}
+
+int cl_batch_profile_read(cl_batch b, double* gemm_ms, double* gemm_flops, int64_t* launches) {
+  if (!b || !gemm_ms || !gemm_flops || !launches) return fail(CL_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(b->st));
+  for (size_t i = 0; i + 1 < b->prof_used; i += 2) {
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, b->prof_ev[i], b->prof_ev[i + 1]));
+    b->prof_ms += ms;
+    b->prof_flop_total += b->prof_flops[i / 2];
+    ++b->prof_launches;
+  }
+  b->prof_used = 0;
+  b->prof_flops.clear();
+  *gemm_ms = b->prof_ms;
+  *gemm_flops = b->prof_flop_total;
+  *launches = b->prof_launches;
+  b->prof_ms = 0;
+  b->prof_flop_total = 0;
+  b->prof_launches = 0;
+  return 0;
+}
+
+int cl_status(cl_batch b, int32_t* out) {
+  if (!b || !out) return fail(CL_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipStreamSynchronize(b->st));
+  HIPCHK(hipMemcpy(out, b->status, sizeof(int32_t) * b->active, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int cl_batch_sync(cl_batch b) {
+  if (!b) return fail(CL_EINVAL, "null batch");
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipStreamSynchronize(b->st));
+  return 0;
+}
+
+void cl_batch_destroy(cl_batch b) {
+  if (!b) return;
+  hipSetDevice(b->device);
+  hipStreamSynchronize(b->st);
+  free_batch(b);
+}
+
+}  // extern "C"

@@ -1,0 +1,42 @@
+"""Error metrics of the GPU-vs-oracle parity tests.
+
+Blocks: relative Frobenius error of every 3x3 selected block,
+    ||Z_b - Z_b^ref||_F / ||Z_b^ref||_F  <= 1e-10.
+Drift: the absolute error of K_{a,x,nu} comes from the rounding of the two blocks P,
+Q of its link (Eq. 8), so it is measured against the size of that link's drift:
+    max_a |K_{a,x,nu} - K^ref_{a,x,nu}| / max_a |K^ref_{a,x,nu}|  <= 1e-10.
+A purely component-wise ratio is ill-conditioned for components far below their
+link's scale (the dense LAPACK oracle itself is only accurate to ~kappa(D)*eps
+in absolute terms), so it is reported but not gated.
+"""
+import numpy as np
+
+TOL = 1e-10
+
+
+def block_errors(got, ref):
+    g = np.asarray(got).reshape(-1, 9)
+    r = np.asarray(ref).reshape(-1, 9)
+    return np.linalg.norm(g - r, axis=1) / np.maximum(np.linalg.norm(r, axis=1), 1e-300)
+
+
+def drift_errors(got, ref):
+    g = np.asarray(got).reshape(-1, 8)
+    r = np.asarray(ref).reshape(-1, 8)
+    scale = np.maximum(np.abs(r).max(axis=1), 1e-300)
+    return np.abs(g - r).max(axis=1) / scale
+
+
+def drift_componentwise(got, ref):
+    g = np.asarray(got).reshape(-1)
+    r = np.asarray(ref).reshape(-1)
+    floor = 1e-6 * np.abs(r).max()
+    return np.abs(g - r) / np.maximum(np.abs(r), floor)
+
+
+def assert_parity(sel, drift, ref_sel, ref_drift, tol=TOL, label=""):
+    be = block_errors(sel, ref_sel)
+    de = drift_errors(drift, ref_drift)
+    assert np.all(np.isfinite(be)) and be.max() <= tol, f"{label} worst block error {be.max():.3e}"
+    assert np.all(np.isfinite(de)) and de.max() <= tol, f"{label} worst drift error {de.max():.3e}"
+    return float(be.max()), float(de.max())

@@ -1,0 +1,160 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Inputs are seeded synthetic SL(3,C) links (paper_1707_08874_amd.inputs); the
+oracle is the dense LAPACK inverse plus the two-block drift (oracle/).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1707_08874_amd import clsel
+from paper_1707_08874_amd.inputs import gen_links, gen_batch, unit_links, pure_gauge_links, eps_for_seed
+from parity import assert_parity, block_errors, drift_errors
+from free_field import free_blocks, pure_gauge_blocks
+
+pytestmark = pytest.mark.gpu
+
+M, MU = 0.05, 0.25
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _run(torch, dims, links, m, mu, graph=False, **plan_kw):
+    """Selected blocks and drift from the GPU for links [B][V][4][3][3] (numpy)."""
+    print(f"\n[gpu] dims={dims} B={links.shape[0]} plan={plan_kw} graph={graph}", flush=True)
+    plan = clsel.Plan(dims, **plan_kw)
+    B = links.shape[0]
+    batch = clsel.Batch(plan, B)
+    lt = torch.from_numpy(np.ascontiguousarray(links)).to("cuda")
+    if graph:
+        batch.use_graph(True)
+        sel, drift = batch.run(lt, m, mu)
+    else:
+        batch.factor(lt, m, mu)
+        batch.selinv()
+        sel = batch.selected()
+        drift = batch.drift()
+    st = batch.status()
+    torch.cuda.synchronize()
+    out = sel.cpu().numpy(), drift.cpu().numpy(), st
+    batch.close()
+    return out
+
+
+def _oracle(links, dims, m, mu):
+    return oracle.selected_and_drift(links, dims, m, mu)
+
+
+@pytest.mark.parametrize("dims,kw", [
+    ((4, 4, 4, 4), {}),                                  # the 4^4 workload, default plan
+    ((4, 4, 4, 4), dict(nb=16, max_pivot_rows=48)),      # chained separators, ragged blocks
+    ((4, 4, 4, 4), dict(nb=1)),                          # one pivot per step
+    ((6, 4, 4, 6), dict(nb=32)),                         # non-cubic, several steps per front
+    ((4, 6, 8, 4), dict(leaf_sites=12, nb=24)),          # larger leaves, odd tile edges
+])
+def test_single_config_matches_oracle(torch_cuda, dims, kw):
+    U = gen_links(dims, 0, 0.1)
+    sel, drift, st = _run(torch_cuda, dims, U[None], M, MU, **kw)
+    assert st.tolist() == [0]
+    ref_sel, ref_drift = _oracle(U, dims, M, MU)
+    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, label=str(dims))
+    print(f"[gpu] worst block {be:.2e} drift {de:.2e}", flush=True)
+
+
+def test_8x8x8x4_plain_matches_oracle(torch_cuda):
+    """The 8^3x4 workload (N = 6144), m = 0.05, mu = 0.25, eps = 0.1, seed 0."""
+    dims = (8, 8, 8, 4)
+    U = gen_links(dims, 0, 0.1)
+    sel, drift, st = _run(torch_cuda, dims, U[None], M, MU)
+    assert st.tolist() == [0]
+    ref_sel, ref_drift = _oracle(U, dims, M, MU)
+    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, label="8^3x4")
+    print(f"[gpu] 8^3x4 worst block {be:.2e} drift {de:.2e}", flush=True)
+
+
+def test_batch_per_config_parameters(torch_cuda):
+    """Four configurations with their own eps, m and mu in one batch; each matches
+    its own oracle, and each equals the same configuration run alone."""
+    dims = (4, 4, 4, 4)
+    seeds = [3, 4, 5, 6]
+    U = gen_batch(dims, seeds)
+    m = np.array([0.02, 0.05, 0.1, 0.05])
+    mu = np.array([0.0, 0.25, 0.4, 0.1])
+    sel, drift, st = _run(torch_cuda, dims, U, m, mu)
+    assert st.tolist() == [0, 0, 0, 0]
+    for b in range(4):
+        ref_sel, ref_drift = _oracle(U[b], dims, m[b], mu[b])
+        assert_parity(sel[b], drift[b], ref_sel, ref_drift, label=f"member {b}")
+    s1, d1, _ = _run(torch_cuda, dims, U[2:3], m[2:3], mu[2:3])
+    assert np.array_equal(s1[0], sel[2]) and np.array_equal(d1[0], drift[2])
+
+
+def test_graph_replay_matches_eager(torch_cuda):
+    """The HIP-graph path gives the same bits as the eager path, over repeated replays
+    with eager work and synchronisation in between."""
+    torch = torch_cuda
+    dims = (4, 4, 4, 4)
+    U = gen_batch(dims, [0, 1])
+    s0, d0, _ = _run(torch, dims, U, M, MU)
+    plan = clsel.Plan(dims)
+    batch = clsel.Batch(plan, 2)
+    batch.use_graph(True)
+    lt = torch.from_numpy(U).to("cuda")
+    so = torch.empty((2, plan.info()["volume"], 9, 3, 3), dtype=torch.complex128, device="cuda")
+    do = torch.empty((2, plan.info()["volume"], 4, 8), dtype=torch.complex128, device="cuda")
+    for rep in range(3):
+        so.zero_()
+        do.zero_()
+        batch.run(lt, M, MU, so, do)
+        torch.cuda.synchronize()
+        assert np.array_equal(so.cpu().numpy(), s0), rep
+        assert np.array_equal(do.cpu().numpy(), d0), rep
+        _ = (lt.abs() * 2).sum().item()  # unrelated eager work between replays
+    batch.close()
+
+
+def test_free_field_and_pure_gauge_closed_forms(torch_cuda):
+    dims = (4, 4, 4, 6)
+    U0 = unit_links(dims)
+    Ug, g = pure_gauge_links(dims, 9)
+    sel, drift, st = _run(torch_cuda, dims, np.stack([U0, Ug]), M, MU)
+    assert st.tolist() == [0, 0]
+    fb = free_blocks(dims, M, MU)
+    pb = pure_gauge_blocks(dims, M, MU, g)
+    assert block_errors(sel[0], fb).max() < 1e-10
+    assert block_errors(sel[1], pb).max() < 1e-10
+    assert np.abs(drift[0]).max() < 1e-10
+    assert np.abs(drift[1]).max() < 1e-9
+
+
+def test_nonfinite_link_is_isolated(torch_cuda):
+    """A configuration with a NaN link reports CL_ENONFINITE and NaN outputs; the
+    other configurations of the batch are unaffected."""
+    dims = (4, 4, 4, 4)
+    U = gen_batch(dims, [0, 1])
+    U[1, 17, 2, 1, 1] = np.nan
+    sel, drift, st = _run(torch_cuda, dims, U, M, MU)
+    assert st[0] == 0 and st[1] == clsel.CL_ENONFINITE
+    assert np.all(np.isnan(sel[1]))
+    ref_sel, ref_drift = _oracle(U[0], dims, M, MU)
+    assert_parity(sel[0], drift[0], ref_sel, ref_drift)
+
+
+def test_call_order_errors(torch_cuda):
+    plan = clsel.Plan((4, 4, 4, 4))
+    batch = clsel.Batch(plan, 1)
+    with pytest.raises(clsel.ClselError) as e:
+        batch.selinv()
+    assert e.value.code == clsel.CL_EORDER
+    with pytest.raises(clsel.ClselError) as e:
+        batch.drift()
+    assert e.value.code == clsel.CL_EORDER
+    batch.close()
