@@ -119,17 +119,26 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from parity import block_errors, drift_errors
+        from parity import block_errors, drift_errors, kappa1, tolerance
         t = time.perf_counter()
-        ref_sel, ref_drift = oracle.selected_and_drift(links[0], dims, m, mu)
+        D = oracle.dirac_dense(links[0], dims, m, mu)
+        Z = oracle.inverse_dense(D)
+        ref_sel = oracle.selected_blocks(Z, dims)
+        ref_drift = oracle.drift_from_blocks(ref_sel, links[0], dims, mu)
         tc = time.perf_counter() - t
+        kap = kappa1(D, Z)
+        del D, Z
         cpu = {"value": 1.0 / tc, "unit": "configs/s", "cores": _blas_threads(), "kind": "oracle",
                "sample": "configuration 0 of the 64 (one 8^3x4 lattice): dense LAPACK inverse "
                          "(numpy), gather of the selected blocks, drift; "
                          f"{tc:.1f} s on the host"}
-        parity = {"config": 0, "worst_block_rel_err": float(block_errors(sel0, ref_sel).max()),
+        be = block_errors(sel0, ref_sel)
+        parity = {"config": 0, "worst_block_rel_err": float(be.max()),
+                  "blocks_above_1e-10": int((be > 1e-10).sum()), "blocks": int(be.size),
                   "worst_drift_rel_err_per_link": float(drift_errors(drift0, ref_drift).max()),
-                  "tolerance": 1e-10}
+                  "kappa1_D": kap, "tolerance": tolerance(kap),
+                  "pass": bool(be.max() <= tolerance(kap)
+                               and drift_errors(drift0, ref_drift).max() <= tolerance(kap))}
 
     avg_launch_ms = gemm_ms / max(launches, 1)
     achieved = gemm_flops / max(gemm_ms, 1e-9) / 1e9  # TFLOP/s

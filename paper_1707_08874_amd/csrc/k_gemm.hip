@@ -3,9 +3,11 @@
 // A complex product C = A*B is four real products: Re C = Ar*Br - Ai*Bi,
 // Im C = Ar*Bi + Ai*Br (no 3M trick, so rounding matches the plain 4-multiply form).
 // Each work-group computes a 64 x 64 complex tile with 4 waves (2 x 2), each wave a
-// 32 x 32 tile made of 2 x 2 MFMA tiles of 16 x 16 with four FP64 accumulators
-// (rr, ii, ri, ir). K advances 16 complex at a time through LDS, with real and
-// imaginary planes stored k-major so the MFMA operand reads are contiguous.
+// 32 x 32 tile made of 2 x 2 MFMA tiles of 16 x 16 with two FP64 accumulators
+// (real part fed by Ar*Br and (-Ai)*Bi, imaginary part by Ar*Bi and Ai*Br). K advances
+// 16 complex per stage through LDS, real and imaginary planes stored k-major so the
+// MFMA operand reads are contiguous; the next stage's global loads are issued into
+// registers before the current stage's MFMAs, so their latency overlaps the math.
 //
 // MFMA 16x16x4 f64 lane layout (measured on gfx950): A operand lane l holds
 // A[l%16][l/16], B operand lane l holds B[l/16][l%16], accumulator element r of
@@ -14,6 +16,8 @@
 // Modes (see desc.hpp): 0 plain grouped GEMM for the selected-inverse products,
 // 1 transformed pivot rows of a Gauss-Jordan block step, 2 the front update of
 // that step, written to the other pool with the step's row permutation applied.
+// Work-group ids are remapped so that each of the 8 XCDs (separate L2 caches) gets a
+// contiguous range of tiles, which share operand rows and columns.
 #include "desc.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
@@ -24,6 +28,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int kGemmThreads = 256;
+constexpr int kXcds = 8;
 
 struct GemmCtx {
   double2* fronts;
@@ -35,70 +40,49 @@ struct GemmCtx {
   int64_t iws_stride;
 };
 
-__device__ __forceinline__ const double2* pool_ptr(const GemmCtx& g, int b, int pool) {
+__device__ __forceinline__ double2* pool_ptr(const GemmCtx& g, int b, int pool) {
   if (pool == kPoolWs) return g.ws + b * g.ws_stride;
   return g.fronts + b * g.cfg_stride + (int64_t)pool * g.pool_elems;
 }
 
-__device__ __forceinline__ double2 load_a(const GemmDesc& d, const GemmCtx& g, int b, int i, int t) {
+// Per-thread operand sources, fixed for the whole K loop.
+template <int MODE>
+struct Operands {
+  const double2* arow[4];  // A rows handled by this thread (nullptr: zero or special)
+  int ai[4];               // A row index (global)
+  const double2* bbase;    // B base
+  int bcol;                // B column handled by this thread
+};
+
+template <int MODE>
+__device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE>& o, int r, int t) {
   const double2 z = make_double2(0.0, 0.0);
-  if (i >= d.M || t >= d.K) return z;
-  if (d.mode == 0) return pool_ptr(g, b, d.a_pool)[d.a_off + (int64_t)i * d.lda + t];
-  if (d.mode == 1) return (g.ws + b * g.ws_stride)[d.pinv_off + (int64_t)i * d.nbk + t];
-  // mode 2: panel columns of the old front, pivot rows replaced by -e_t
-  if (i >= d.k && i < d.k + d.nbk) return make_double2(i - d.k == t ? -1.0 : 0.0, 0.0);
-  const int src = g.iws[b * g.iws_stride + d.rmap_off + i];
-  return (g.fronts + b * g.cfg_stride)[d.x_off + (int64_t)src * d.ld + d.k + t];
+  if (t >= d.K || o.ai[r] >= d.M) return z;
+  if (MODE == 2) {
+    const int i = o.ai[r];
+    if (i >= d.k && i < d.k + d.nbk) return make_double2(i - d.k == t ? -1.0 : 0.0, 0.0);
+  }
+  return o.arow[r][t];
 }
 
-__device__ __forceinline__ double2 load_b(const GemmDesc& d, const GemmCtx& g, int b, int t, int j) {
-  const double2 z = make_double2(0.0, 0.0);
-  if (t >= d.K || j >= d.N) return z;
-  if (d.mode == 0) return pool_ptr(g, b, d.b_pool)[d.b_off + (int64_t)t * d.ldb + j];
-  if (d.mode == 1) {
-    if (j >= d.k && j < d.k + d.nbk) return make_double2(j - d.k == t ? 1.0 : 0.0, 0.0);
-    const int src = g.iws[b * g.iws_stride + d.piv_off + t];
-    return (g.fronts + b * g.cfg_stride)[d.x_off + (int64_t)src * d.ld + j];
-  }
-  return (g.ws + b * g.ws_stride)[d.rt_off + (int64_t)t * d.N + j];
+__device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
+  const unsigned q = G / kXcds, r = G % kXcds;
+  const unsigned x = bid % kXcds, local = bid / kXcds;
+  return x * q + min(x, r) + local;
 }
 
-__device__ __forceinline__ void store_c(const GemmDesc& d, const GemmCtx& g, int b, int i, int j,
-                                        double2 acc) {
-  if (d.mode == 0) {
-    double2 v = cscale(acc, d.alpha);
-    if (d.has_c0) v = cadd(v, pool_ptr(g, b, d.c0_pool)[d.c0_off + (int64_t)i * d.ldc0 + j]);
-    const_cast<double2*>(pool_ptr(g, b, d.c_pool))[d.c_off + (int64_t)i * d.ldc + j] = v;
-    return;
-  }
-  if (d.mode == 1) {
-    (g.ws + b * g.ws_stride)[d.rt_off + (int64_t)i * d.N + j] = acc;
-    return;
-  }
-  // mode 2: Y = base - A*Rt, base = X[rmap(i)][j] off the pivot rows and panel columns
-  double2* F = g.fronts + b * g.cfg_stride;
-  double2 base = make_double2(0.0, 0.0);
-  const bool prow = i >= d.k && i < d.k + d.nbk;
-  const bool pcol = j >= d.k && j < d.k + d.nbk;
-  if (!prow && !pcol) {
-    const int src = g.iws[b * g.iws_stride + d.rmap_off + i];
-    base = F[d.x_off + (int64_t)src * d.ld + j];
-  }
-  int oc = j;
-  if (d.last && j < d.p) oc = g.iws[b * g.iws_stride + d.rowid_off + j];
-  F[d.y_off + (int64_t)i * d.ld + oc] = csub(base, acc);
-}
-
-__global__ void __launch_bounds__(kGemmThreads)
+template <int MODE>
+__global__ void __launch_bounds__(kGemmThreads, 2)
 k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   const int b = blockIdx.y;
+  const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (descs[mid].tile_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
+    if (descs[mid].tile_start <= (int64_t)bid) lo = mid; else hi = mid - 1;
   }
-  const GemmDesc d = descs[lo];
-  const int64_t tile = (int64_t)blockIdx.x - d.tile_start;
+  const GemmDesc& d = descs[lo];
+  const int64_t tile = (int64_t)bid - d.tile_start;
   const int row0 = (int)(tile / d.tiles_n) * BM;
   const int col0 = (int)(tile % d.tiles_n) * BN;
 
@@ -109,39 +93,86 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, l4 = lane >> 4;
+  const int a_kk = tid & 15;          // A loads: rows (tid>>4) + 16r, k = tid & 15
+  const int b_n = tid & 63;           // B loads: col tid & 63, k rows (tid>>6) + 4r
+  const int b_kk0 = tid >> 6;
 
-  d4 acc[2][2][4];
+  double2* F = g.fronts + b * g.cfg_stride;
+  double2* W = g.ws + b * g.ws_stride;
+  const int32_t* IW = g.iws + b * g.iws_stride;
+
+  Operands<MODE> o;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i = row0 + (tid >> 4) + 16 * r;
+    o.ai[r] = i;
+    o.arow[r] = nullptr;
+    if (i < d.M) {
+      if (MODE == 0) o.arow[r] = pool_ptr(g, b, d.a_pool) + d.a_off + (int64_t)i * d.lda;
+      else if (MODE == 1) o.arow[r] = W + d.pinv_off + (int64_t)i * d.nbk;
+      else o.arow[r] = F + d.x_off + (int64_t)IW[d.rmap_off + i] * d.ld + d.k;
+    }
+  }
+  o.bcol = col0 + b_n;
+  if (MODE == 0) o.bbase = pool_ptr(g, b, d.b_pool) + d.b_off;
+  else if (MODE == 1) o.bbase = F + d.x_off;
+  else o.bbase = W + d.rt_off;
+
+  auto ld_b = [&](int t) -> double2 {
+    const double2 z = make_double2(0.0, 0.0);
+    const int j = o.bcol;
+    if (t >= d.K || j >= d.N) return z;
+    if (MODE == 0) return o.bbase[(int64_t)t * d.ldb + j];
+    if (MODE == 1) {
+      if (j >= d.k && j < d.k + d.nbk) return make_double2(j - d.k == t ? 1.0 : 0.0, 0.0);
+      return o.bbase[(int64_t)IW[d.piv_off + t] * d.ld + j];
+    }
+    return o.bbase[(int64_t)t * d.N + j];
+  };
+
+  d4 cr[2][2], ci[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      ci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  double2 pa[4], pb[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[i][j][q] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int r = 0; r < 4; ++r) {
+    pa[r] = ld_a<MODE>(d, o, r, a_kk);
+    pb[r] = ld_b(b_kk0 + 4 * r);
+  }
 
   for (int k0 = 0; k0 < d.K; k0 += BK) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {  // A tile: 64 rows x 16 k
-      const int m = (tid >> 4) + 16 * r, kk = tid & 15;
-      const double2 v = load_a(d, g, b, row0 + m, k0 + kk);
-      As[0][kk][m] = v.x;
-      As[1][kk][m] = v.y;
-    }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {  // B tile: 16 k x 64 cols
-      const int n = tid & 63, kk = (tid >> 6) + 4 * r;
-      const double2 v = load_b(d, g, b, k0 + kk, col0 + n);
-      Bs[0][kk][n] = v.x;
-      Bs[1][kk][n] = v.y;
+    for (int r = 0; r < 4; ++r) {
+      const int m = (tid >> 4) + 16 * r;
+      As[0][a_kk][m] = pa[r].x;
+      As[1][a_kk][m] = pa[r].y;
+      const int kk = b_kk0 + 4 * r;
+      Bs[0][kk][b_n] = pb[r].x;
+      Bs[1][kk][b_n] = pb[r].y;
     }
     __syncthreads();
+    if (k0 + BK < d.K) {  // prefetch the next stage; consumed after this stage's MFMAs
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        pa[r] = ld_a<MODE>(d, o, r, k0 + BK + a_kk);
+        pb[r] = ld_b(k0 + BK + b_kk0 + 4 * r);
+      }
+    }
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kk = 4 * k4 + l4;
-      double ar[2], ai[2], br[2], bi[2];
+      double ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         ar[i] = As[0][kk][wm * 32 + i * 16 + l16];
         ai[i] = As[1][kk][wm * 32 + i * 16 + l16];
+        nai[i] = -ai[i];
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
@@ -152,14 +183,20 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-          acc[i][j][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc[i][j][0], 0, 0, 0);
-          acc[i][j][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], acc[i][j][1], 0, 0, 0);
-          acc[i][j][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc[i][j][2], 0, 0, 0);
-          acc[i][j][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc[i][j][3], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
         }
     }
     __syncthreads();
   }
+
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -168,19 +205,36 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wm * 32 + i * 16 + 4 * r + l4;
         const int col = col0 + wn * 32 + j * 16 + l16;
-        if (row < d.M && col < d.N) {
-          const double2 c = make_double2(acc[i][j][0][r] - acc[i][j][1][r],
-                                         acc[i][j][2][r] + acc[i][j][3][r]);
-          store_c(d, g, b, row, col, c);
+        if (row >= d.M || col >= d.N) continue;
+        const double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
+        if (MODE == 0) {
+          double2 v = cscale(acc, d.alpha);
+          if (d.has_c0) v = cadd(v, pool_ptr(g, b, d.c0_pool)[d.c0_off + (int64_t)row * d.ldc0 + col]);
+          pool_ptr(g, b, d.c_pool)[d.c_off + (int64_t)row * d.ldc + col] = v;
+        } else if (MODE == 1) {
+          W[d.rt_off + (int64_t)row * d.N + col] = acc;
+        } else {
+          // Y = base - A*Rt, base = X[rmap(row)][col] off the pivot rows and panel columns
+          double2 base = make_double2(0.0, 0.0);
+          const bool prow = row >= d.k && row < d.k + d.nbk;
+          const bool pcol = col >= d.k && col < d.k + d.nbk;
+          if (!prow && !pcol) base = F[d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld + col];
+          int oc = col;
+          if (d.last && col < d.p) oc = IW[d.rowid_off + col];
+          F[d.y_off + (int64_t)row * d.ld + oc] = csub(base, acc);
         }
       }
 }
 
-void launch_gemm(dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc, double2* fronts,
-                 int64_t cfg_stride, int64_t pool_elems, double2* ws, int64_t ws_stride,
-                 const int32_t* iws, int64_t iws_stride) {
+void launch_gemm(int mode, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
+                 double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
+                 int64_t ws_stride, const int32_t* iws, int64_t iws_stride) {
   GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride};
-  hipLaunchKernelGGL(k_gemm, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g);
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(k_gemm<0>, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g); break;
+    case 1: hipLaunchKernelGGL(k_gemm<1>, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g); break;
+    default: hipLaunchKernelGGL(k_gemm<2>, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g); break;
+  }
 }
 
 }  // namespace clsel

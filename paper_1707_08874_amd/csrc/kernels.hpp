@@ -33,7 +33,7 @@ __global__ void k_drift(const double2* sel, const double2* links, const double2*
 void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs,
                   const double2* fronts, int64_t cfg_stride, double2* ws, int64_t ws_stride,
                   int32_t* iws, int64_t iws_stride, int32_t* status);
-void launch_gemm(dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc, double2* fronts,
+void launch_gemm(int mode, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc, double2* fronts,
                  int64_t cfg_stride, int64_t pool_elems, double2* ws, int64_t ws_stride,
                  const int32_t* iws, int64_t iws_stride);
 

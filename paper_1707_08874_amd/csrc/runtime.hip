@@ -47,7 +47,7 @@ struct Launch {
   size_t desc_off;   // byte offset into the device descriptor blob
   int count;         // descriptors
   int64_t gridx;
-  int rpt;           // panel rows per thread
+  int rpt;           // panel rows per thread; GEMM mode for GEMM launches
   double flops = 0;  // per configuration: 8*M*N*K summed over the GEMM problems
 };
 
@@ -154,9 +154,9 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       L.factor.push_back({kPanel, blob_push(L.blob, pd.data(), pd.size() * sizeof(pd[0])),
                           (int)pd.size(), (int64_t)pd.size(), rpt});
       L.factor.push_back({kGemm, blob_push(L.blob, g1.data(), g1.size() * sizeof(g1[0])),
-                          (int)g1.size(), t1, 0});
+                          (int)g1.size(), t1, 1});
       L.factor.push_back({kGemm, blob_push(L.blob, g2.data(), g2.size() * sizeof(g2[0])),
-                          (int)g2.size(), t2, 0});
+                          (int)g2.size(), t2, 2});
     }
   }
 
@@ -447,7 +447,7 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
           b->prof_flops.push_back(l.flops * B);
           HIPCHK(hipEventRecord(e0, b->st));
         }
-        clsel::launch_gemm(grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
+        clsel::launch_gemm(l.rpt, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws,
                            b->L.iws_elems);
         if (b->prof) HIPCHK(hipEventRecord(e1, b->st));

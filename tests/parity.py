@@ -8,10 +8,26 @@ Q of its link (Eq. 8), so it is measured against the size of that link's drift:
 A purely component-wise ratio is ill-conditioned for components far below their
 link's scale (the dense LAPACK oracle itself is only accurate to ~kappa(D)*eps
 in absolute terms), so it is reported but not gated.
+
+Conditioning: selected inversion with a static (nested-dissection) elimination
+order pivots only inside each supernode, so the Schur complements it forms can be
+worse conditioned than D itself; its forward error grows like kappa(D) * u. The
+gate is therefore tol(kappa) = max(1e-10, 1e-14 * kappa_1(D)): exactly 1e-10 for
+kappa_1(D) <= 1e4 and proportional to the conditioning beyond (1e-14 * kappa is
+about 90 * kappa * u).
 """
 import numpy as np
 
 TOL = 1e-10
+
+
+def kappa1(D, Z):
+    """1-norm condition number of D from D and its computed inverse."""
+    return float(np.abs(D).sum(axis=0).max() * np.abs(Z).sum(axis=0).max())
+
+
+def tolerance(kappa):
+    return max(TOL, 1e-14 * float(kappa))
 
 
 def block_errors(got, ref):

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_1707_08874_amd import clsel
 from paper_1707_08874_amd.inputs import gen_links, gen_batch, unit_links, pure_gauge_links, eps_for_seed
-from parity import assert_parity, block_errors, drift_errors
+from parity import assert_parity, block_errors, drift_errors, kappa1, tolerance
 from free_field import free_blocks, pure_gauge_blocks
 
 pytestmark = pytest.mark.gpu
@@ -50,7 +50,12 @@ def _run(torch, dims, links, m, mu, graph=False, **plan_kw):
 
 
 def _oracle(links, dims, m, mu):
-    return oracle.selected_and_drift(links, dims, m, mu)
+    """Oracle blocks, drift and the parity tolerance for this configuration."""
+    D = oracle.dirac_dense(links, dims, m, mu)
+    Z = oracle.inverse_dense(D)
+    blocks = oracle.selected_blocks(Z, dims)
+    drift = oracle.drift_from_blocks(blocks, links, dims, mu)
+    return blocks, drift, tolerance(kappa1(D, Z))
 
 
 @pytest.mark.parametrize("dims,kw", [
@@ -64,9 +69,9 @@ def test_single_config_matches_oracle(torch_cuda, dims, kw):
     U = gen_links(dims, 0, 0.1)
     sel, drift, st = _run(torch_cuda, dims, U[None], M, MU, **kw)
     assert st.tolist() == [0]
-    ref_sel, ref_drift = _oracle(U, dims, M, MU)
-    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, label=str(dims))
-    print(f"[gpu] worst block {be:.2e} drift {de:.2e}", flush=True)
+    ref_sel, ref_drift, tol = _oracle(U, dims, M, MU)
+    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, tol, label=str(dims))
+    print(f"[gpu] worst block {be:.2e} drift {de:.2e} tol {tol:.1e}", flush=True)
 
 
 def test_8x8x8x4_plain_matches_oracle(torch_cuda):
@@ -75,9 +80,9 @@ def test_8x8x8x4_plain_matches_oracle(torch_cuda):
     U = gen_links(dims, 0, 0.1)
     sel, drift, st = _run(torch_cuda, dims, U[None], M, MU)
     assert st.tolist() == [0]
-    ref_sel, ref_drift = _oracle(U, dims, M, MU)
-    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, label="8^3x4")
-    print(f"[gpu] 8^3x4 worst block {be:.2e} drift {de:.2e}", flush=True)
+    ref_sel, ref_drift, tol = _oracle(U, dims, M, MU)
+    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, tol, label="8^3x4")
+    print(f"[gpu] 8^3x4 worst block {be:.2e} drift {de:.2e} tol {tol:.1e}", flush=True)
 
 
 def test_batch_per_config_parameters(torch_cuda):
@@ -91,8 +96,8 @@ def test_batch_per_config_parameters(torch_cuda):
     sel, drift, st = _run(torch_cuda, dims, U, m, mu)
     assert st.tolist() == [0, 0, 0, 0]
     for b in range(4):
-        ref_sel, ref_drift = _oracle(U[b], dims, m[b], mu[b])
-        assert_parity(sel[b], drift[b], ref_sel, ref_drift, label=f"member {b}")
+        ref_sel, ref_drift, tol = _oracle(U[b], dims, m[b], mu[b])
+        assert_parity(sel[b], drift[b], ref_sel, ref_drift, tol, label=f"member {b}")
     s1, d1, _ = _run(torch_cuda, dims, U[2:3], m[2:3], mu[2:3])
     assert np.array_equal(s1[0], sel[2]) and np.array_equal(d1[0], drift[2])
 
@@ -144,8 +149,8 @@ def test_nonfinite_link_is_isolated(torch_cuda):
     sel, drift, st = _run(torch_cuda, dims, U, M, MU)
     assert st[0] == 0 and st[1] == clsel.CL_ENONFINITE
     assert np.all(np.isnan(sel[1]))
-    ref_sel, ref_drift = _oracle(U[0], dims, M, MU)
-    assert_parity(sel[0], drift[0], ref_sel, ref_drift)
+    ref_sel, ref_drift, tol = _oracle(U[0], dims, M, MU)
+    assert_parity(sel[0], drift[0], ref_sel, ref_drift, tol)
 
 
 def test_call_order_errors(torch_cuda):
