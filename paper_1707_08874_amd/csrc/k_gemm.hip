@@ -146,7 +146,27 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     pb[r] = ld_b(b_kk0 + 4 * r);
   }
 
-  for (int k0 = 0; k0 < d.K; k0 += BK) {
+  // mode 2: the old front values that the update is subtracted from, loaded during the
+  // last K stage so the loads overlap its MFMAs
+  double2 base[2][2][4];
+  auto load_base = [&]() {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * 32 + i * 16 + 4 * r + l4;
+        const bool rok = row < d.M && !(row >= d.k && row < d.k + d.nbk);
+        const double2* xr = rok ? F + d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld : nullptr;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int col = col0 + wn * 32 + j * 16 + l16;
+          const bool ok = rok && col < d.N && !(col >= d.k && col < d.k + d.nbk);
+          base[i][j][r] = ok ? xr[col] : make_double2(0.0, 0.0);
+        }
+      }
+  };
+
+  auto store_stage = [&]() {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int m = (tid >> 4) + 16 * r;
@@ -156,14 +176,8 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       Bs[0][kk][b_n] = pb[r].x;
       Bs[1][kk][b_n] = pb[r].y;
     }
-    __syncthreads();
-    if (k0 + BK < d.K) {  // prefetch the next stage; consumed after this stage's MFMAs
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        pa[r] = ld_a<MODE>(d, o, r, k0 + BK + a_kk);
-        pb[r] = ld_b(k0 + BK + b_kk0 + 4 * r);
-      }
-    }
+  };
+  auto mfma_stage = [&]() {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kk = 4 * k4 + l4;
@@ -194,8 +208,26 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
           ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
         }
     }
+  };
+
+  // all stages but the last: store the prefetched stage, prefetch the next, MFMAs
+  const int klast = ((d.K - 1) / BK) * BK;
+  for (int k0 = 0; k0 < klast; k0 += BK) {
+    store_stage();
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      pa[r] = ld_a<MODE>(d, o, r, k0 + BK + a_kk);
+      pb[r] = ld_b(k0 + BK + b_kk0 + 4 * r);
+    }
+    mfma_stage();
     __syncthreads();
   }
+  // last stage; mode 2 fetches its subtrahend here so the loads overlap the MFMAs
+  store_stage();
+  __syncthreads();
+  if (MODE == 2) load_base();
+  mfma_stage();
 
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -215,13 +247,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
           W[d.rt_off + (int64_t)row * d.N + col] = acc;
         } else {
           // Y = base - A*Rt, base = X[rmap(row)][col] off the pivot rows and panel columns
-          double2 base = make_double2(0.0, 0.0);
-          const bool prow = row >= d.k && row < d.k + d.nbk;
-          const bool pcol = col >= d.k && col < d.k + d.nbk;
-          if (!prow && !pcol) base = F[d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld + col];
           int oc = col;
           if (d.last && col < d.p) oc = IW[d.rowid_off + col];
-          F[d.y_off + (int64_t)row * d.ld + oc] = csub(base, acc);
+          F[d.y_off + (int64_t)row * d.ld + oc] = csub(base[i][j][r], acc);
         }
       }
 }

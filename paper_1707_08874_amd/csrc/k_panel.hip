@@ -45,10 +45,10 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   __shared__ int s_at[kMaxPivotRows];
   __shared__ int s_pos[kMaxPivotRows];
 
-  for (int64_t e = tid; e < (int64_t)cand * nbk; e += kPanelThreads) {
-    const int i = (int)(e / nbk), c = (int)(e % nbk);
-    PW[e] = X[(int64_t)(k + i) * ld + k + c];
-  }
+  // Column group 0 is read straight from the front; the lazy update after each group
+  // writes the later groups of the unused rows to PW (row-major, ld nbk), which is
+  // where groups >= 1 are read from.
+  const double2* Xp = X + (int64_t)k * ld + k;  // candidate row 0, panel column 0
   if (tid == 0) s_flag = 0;
   __syncthreads();
 
@@ -63,10 +63,11 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
 #pragma unroll
     for (int j = 0; j < RPT; ++j) {
       const int r = tid + j * kPanelThreads;
+      const bool live = r < cand && !used[j];
+      const double2* src = g0 == 0 ? Xp + (int64_t)r * ld : PW + (int64_t)r * nbk + g0;
 #pragma unroll
       for (int c = 0; c < kGroup; ++c)
-        cur[j][c] = (r < cand && !used[j] && c < gw) ? PW[(int64_t)r * nbk + g0 + c]
-                                                       : make_double2(0.0, 0.0);
+        cur[j][c] = (live && c < gw) ? src[c] : make_double2(0.0, 0.0);
     }
     for (int c = 0; c < gw; ++c) {
       double best = -1.0;
@@ -137,19 +138,33 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
     if (nrest > 0) {
       for (int e = tid; e < gw * nrest; e += kPanelThreads) {
         const int t = e / nrest, cc = e % nrest;
-        s_buf[t * kMaxNB + cc] = PW[(int64_t)s_piv[g0 + t] * nbk + rest0 + cc];
+        const int pr = s_piv[g0 + t];
+        s_buf[t * kMaxNB + cc] = g0 == 0 ? Xp[(int64_t)pr * ld + rest0 + cc]
+                                         : PW[(int64_t)pr * nbk + rest0 + cc];
       }
       __syncthreads();
+      constexpr int kChunk = RPT >= 2 ? 4 : 8;  // independent loads in flight per row
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         const int r = tid + j * kPanelThreads;
         if (r < cand && !used[j]) {
-          for (int cc = 0; cc < nrest; ++cc) {
-            double2 acc = PW[(int64_t)r * nbk + rest0 + cc];
+          const double2* src = g0 == 0 ? Xp + (int64_t)r * ld + rest0 : PW + (int64_t)r * nbk + rest0;
+          double2* dst = PW + (int64_t)r * nbk + rest0;
+          for (int c0 = 0; c0 < nrest; c0 += kChunk) {
+            double2 acc[kChunk];
 #pragma unroll
-            for (int t = 0; t < kGroup; ++t)
-              if (t < gw) acc = cfma(acc, cur[j][t], s_buf[t * kMaxNB + cc]);
-            PW[(int64_t)r * nbk + rest0 + cc] = acc;
+            for (int q = 0; q < kChunk; ++q)
+              acc[q] = (c0 + q < nrest) ? src[c0 + q] : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q) {
+              const int cc = c0 + q;
+              if (cc < nrest) {
+#pragma unroll
+                for (int t = 0; t < kGroup; ++t)
+                  if (t < gw) acc[q] = cfma(acc[q], cur[j][t], s_buf[t * kMaxNB + cc]);
+                dst[cc] = acc[q];
+              }
+            }
           }
         }
       }
@@ -159,12 +174,21 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
 
   // ---- phase 2: Pi^{-1} by Gauss-Jordan in LDS (rows already in pivot order)
   __syncthreads();
-  for (int e = tid; e < nbk * nbk; e += kPanelThreads) {
-    const int t = e / nbk, c = e % nbk;
-    s_buf[t * kPiLd + c] = X[(int64_t)(k + s_piv[t]) * ld + k + c];
+  constexpr int kPer = (kMaxNB * kMaxNB + kPanelThreads - 1) / kPanelThreads;
+  {
+    double2 v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kPanelThreads;
+      v[q] = e < nbk * nbk ? Xp[(int64_t)s_piv[e / nbk] * ld + e % nbk] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + q * kPanelThreads;
+      if (e < nbk * nbk) s_buf[(e / nbk) * kPiLd + e % nbk] = v[q];
+    }
   }
   __syncthreads();
-  constexpr int kPer = (kMaxNB * kMaxNB + kPanelThreads - 1) / kPanelThreads;
   for (int c = 0; c < nbk; ++c) {
     double2 dp = s_buf[c * kPiLd + c];
     if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) {
