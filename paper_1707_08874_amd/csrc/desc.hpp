@@ -18,7 +18,8 @@ enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2 };
 
 // Front assembly: one entry per (front) of a level.
 struct AsmDesc {
-  int64_t off;            // front offset (pool 0 receives the assembled front)
+  int64_t off;            // front offset: update rows are assembled into pool 0
+  int64_t joff;           // front offset incl. pool for the pivot rows
   int64_t site_off;       // into front_sites
   int64_t blk_start;      // first 256-element block of this front in the launch
   int H, p, ld, nchild;

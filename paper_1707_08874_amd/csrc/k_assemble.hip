@@ -1,9 +1,10 @@
 // Link inverses and front assembly.
 //
-// The staggered operator (hopping blocks c+ U and -c- U^{-1}, Sec. 2, Eq. 1, with the
-// explicit form fixed in the project docs) is never stored as a sparse matrix: each
-// front pulls the entries it owns straight from the links, plus the update (Schur)
-// blocks of its children, in one deterministic pass (no atomics).
+// The staggered operator of Eq. 1 (diagonal m, hopping blocks c+ U and -c- U^{-1}, as
+// written out in include/clsel.h) is never stored as a sparse matrix: each front pulls
+// the entries it owns straight from the links, plus the update (Schur) blocks of its
+// children, in one deterministic pass (no atomics). Pivot rows go to the pool where
+// the Gauss-Jordan sweep starts, update rows to pool 0.
 #include "desc.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
@@ -104,7 +105,7 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     v = cadd(v, dirac_entry(x, I % 3, y, J % 3, links + b * link_cfg_stride,
                             linv + b * link_cfg_stride, mvals[b], exp(mu), exp(-mu), dims));
   }
-  F[d.off + (int64_t)I * d.ld + J] = v;
+  F[(I < d.p ? d.joff : d.off) + (int64_t)I * d.ld + J] = v;
   if (e < d.p) iws[b * iws_stride + d.rowid_off + e] = (int32_t)e;
 }
 

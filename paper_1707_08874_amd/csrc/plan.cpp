@@ -226,9 +226,13 @@ int build_plan(const int32_t dims[4], const PlanOptions& opt, Plan& P, std::stri
     for (int i = 0; i < fr.nchild; ++i) lev = std::max(lev, F[fr.child[i]].level + 1);
     fr.level = lev;
     maxlev = std::max(maxlev, lev);
+    // The pivot rows ping-pong between the pools once per block step and must end in
+    // pool 1, where the update rows' results are written from their assembled values in
+    // pool 0; the selected-inverse front then reuses pool 0.
     fr.nsteps = (fr.p + opt.nb - 1) / opt.nb;
-    fr.fbuf = fr.nsteps % 2;
-    fr.zbuf = (fr.s == 0) ? fr.fbuf : 1 - fr.fbuf;
+    fr.jbuf = (fr.nsteps % 2 == 0) ? 1 : 0;
+    fr.fbuf = 1;
+    fr.zbuf = (fr.s == 0) ? fr.fbuf : 0;
     P.max_steps = std::max(P.max_steps, fr.nsteps);
     P.max_H = std::max(P.max_H, fr.H);
     P.max_p = std::max(P.max_p, fr.p);

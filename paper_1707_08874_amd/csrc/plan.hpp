@@ -39,7 +39,8 @@ struct Front {
   int64_t inv_off[kMaxChildren] = {0, 0, 0, 0};  // per child: H entries, row -> child update row or -1
   int64_t rel_off = 0;      // s entries: update row -> row of the parent front
   int nsteps = 0;           // ceil(p / nb)
-  int fbuf = 0;             // pool holding the factorised front (0 or 1)
+  int jbuf = 0;             // pool receiving the assembled pivot rows (the sweep ends in pool 1)
+  int fbuf = 1;             // pool holding the factorised front
   int zbuf = 0;             // pool holding the selected-inverse front
 };
 

@@ -91,7 +91,8 @@ void build_layout(const clsel::Plan& P, Layout& L) {
     for (int f : fl) {
       const clsel::Front& fr = P.fronts[f];
       clsel::AsmDesc d{};
-      d.off = fr.off;  // pool 0
+      d.off = fr.off;  // update rows: pool 0
+      d.joff = fr.jbuf * pool + fr.off;
       d.site_off = fr.site_off;
       d.blk_start = blk;
       blk += cdiv64((int64_t)fr.H * fr.H, 256);
@@ -122,7 +123,8 @@ void build_layout(const clsel::Plan& P, Layout& L) {
         const int k = q * nb, nbk = std::min(nb, fr.p - k), cand = fr.p - k;
         rpt = std::max(rpt, (int)cdiv64(cand, 512));
         clsel::PanelDesc p{};
-        p.x_off = (q % 2) * pool + fr.off;
+        const int xin = fr.jbuf ^ (q % 2);
+        p.x_off = xin * pool + fr.off;
         p.pw_off = wso; wso += (int64_t)cand * nbk;
         p.pinv_off = wso; wso += (int64_t)nbk * nbk;
         const int64_t rt_off = wso; wso += (int64_t)nbk * fr.H;
@@ -138,14 +140,15 @@ void build_layout(const clsel::Plan& P, Layout& L) {
         a.tiles_n = (int)cdiv64(fr.H, 64);
         a.tile_start = t1; t1 += a.tiles_n;
         a.k = k; a.nbk = nbk; a.p = fr.p; a.ld = fr.ld; a.last = 0;
-        a.x_off = p.x_off; a.y_off = ((q + 1) % 2) * pool + fr.off;
+        a.x_off = p.x_off; a.y_off = (xin ^ 1) * pool + fr.off;
         a.rt_off = rt_off; a.pinv_off = p.pinv_off; a.piv_off = p.piv_off;
         a.rmap_off = p.rmap_off; a.rowid_off = p.rowid_off;
         g1.push_back(a);
+        // only the pivot rows are swept; the update rows are finished after the sweep
         clsel::GemmDesc u = a;
-        u.mode = 2; u.M = fr.H; u.N = fr.H; u.K = nbk;
+        u.mode = 2; u.M = fr.p; u.N = fr.H; u.K = nbk;
         u.tiles_n = (int)cdiv64(fr.H, 64);
-        u.tile_start = t2; t2 += cdiv64(fr.H, 64) * u.tiles_n;
+        u.tile_start = t2; t2 += cdiv64(fr.p, 64) * u.tiles_n;
         u.last = (q == fr.nsteps - 1) ? 1 : 0;
         g2.push_back(u);
       }
@@ -158,6 +161,39 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       L.factor.push_back({kGemm, blob_push(L.blob, g2.data(), g2.size() * sizeof(g2[0])),
                           (int)g2.size(), t2, 2});
     }
+    // update rows of every front of the level, from their assembled values (pool 0)
+    // and the swept pivot rows (pool 1):
+    //   S-block  = A_SS - A_SJ * U^     with U^ = A_JJ^{-1} A_JS
+    //   SJ-block = -A_SJ * A_JJ^{-1}    (= -L^)
+    std::vector<clsel::GemmDesc> gs;
+    int64_t ts = 0;
+    for (int f : fl) {
+      const clsel::Front& fr = P.fronts[f];
+      if (fr.s == 0) continue;
+      const int64_t o = fr.off, p = fr.p, ld = fr.ld;
+      clsel::GemmDesc ss{};
+      ss.mode = 0; ss.M = fr.s; ss.N = fr.s; ss.K = fr.p;
+      ss.a_pool = 0; ss.a_off = o + p * ld; ss.lda = (int)ld;
+      ss.b_pool = 1; ss.b_off = o + p; ss.ldb = (int)ld;
+      ss.c_pool = 1; ss.c_off = o + p * ld + p; ss.ldc = (int)ld;
+      ss.c0_pool = 0; ss.c0_off = o + p * ld + p; ss.ldc0 = (int)ld;
+      ss.alpha = -1.0; ss.has_c0 = 1;
+      ss.tiles_n = (int)cdiv64(ss.N, 64);
+      ss.tile_start = ts; ts += cdiv64(ss.M, 64) * ss.tiles_n;
+      gs.push_back(ss);
+      clsel::GemmDesc sj{};
+      sj.mode = 0; sj.M = fr.s; sj.N = fr.p; sj.K = fr.p;
+      sj.a_pool = 0; sj.a_off = o + p * ld; sj.lda = (int)ld;
+      sj.b_pool = 1; sj.b_off = o; sj.ldb = (int)ld;
+      sj.c_pool = 1; sj.c_off = o + p * ld; sj.ldc = (int)ld;
+      sj.alpha = -1.0; sj.has_c0 = 0;
+      sj.tiles_n = (int)cdiv64(sj.N, 64);
+      sj.tile_start = ts; ts += cdiv64(sj.M, 64) * sj.tiles_n;
+      gs.push_back(sj);
+    }
+    if (!gs.empty())
+      L.factor.push_back({kGemm, blob_push(L.blob, gs.data(), gs.size() * sizeof(gs[0])),
+                          (int)gs.size(), ts, 0});
   }
 
   // selected inversion, root level first
@@ -250,6 +286,7 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
         REQ(d[i].blk_start == blk, "asm block start", d[i].blk_start, blk);
         blk += cdiv64((int64_t)d[i].H * d[i].H, 256);
         REQ(d[i].off + (int64_t)d[i].H * d[i].ld <= pool, "asm front", d[i].off, pool);
+        REQ(d[i].joff + (int64_t)d[i].p * d[i].ld <= two, "asm pivot rows", d[i].joff, two);
         REQ(d[i].site_off + d[i].H / 3 <= (int64_t)P.front_sites.size(), "asm sites", d[i].site_off, 0);
         REQ(d[i].rowid_off + d[i].p <= rowid_total, "asm rowid", d[i].rowid_off, rowid_total);
         for (int c = 0; c < d[i].nchild; ++c) {
@@ -294,12 +331,13 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
           REQ(g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N <= lim(g.c_pool), "gemm C", g.c_off, lim(g.c_pool));
           if (g.has_c0) REQ(g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N <= lim(g.c0_pool), "gemm C0", g.c0_off, 0);
         } else {
-          const int H = g.mode == 1 ? g.N : g.M;
+          const int H = g.N;  // both modes span every column of the front
           REQ(g.x_off + (int64_t)H * g.ld <= two && g.y_off + (int64_t)H * g.ld <= two, "gemm front", g.x_off, two);
           REQ(g.rt_off + (int64_t)g.nbk * H <= L.ws_elems, "gemm Rt", g.rt_off, L.ws_elems);
           REQ(g.pinv_off + (int64_t)g.nbk * g.nbk <= L.ws_elems, "gemm pinv", g.pinv_off, L.ws_elems);
           REQ(g.piv_off + g.nbk <= L.iws_elems && g.rmap_off + H <= L.iws_elems, "gemm maps", g.rmap_off, L.iws_elems);
           REQ(g.K == g.nbk && g.k + g.nbk <= g.p && g.p <= H, "gemm step", g.k, g.p);
+          REQ(g.mode == 1 ? g.M == g.nbk : g.M == g.p, "gemm rows", g.M, g.p);
         }
       }
       REQ(t == l.gridx, "gemm grid", t, l.gridx);
