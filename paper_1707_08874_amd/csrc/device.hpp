@@ -22,18 +22,15 @@ __device__ __forceinline__ double2 cfma(double2 c, double2 a, double2 b) {
 __device__ __forceinline__ double2 cscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
 __device__ __forceinline__ double cabs2(double2 a) { return a.x * a.x + a.y * a.y; }
 
-// 1/d by Smith's algorithm (R. L. Smith, "Algorithm 116: Complex division", 1962),
-// which avoids overflow and underflow of |d|^2.
+// 1/d = conj(d) / |d|^2 with d first scaled by an exact power of two so that |d|^2
+// can neither overflow nor underflow; one division instead of the three of Smith's
+// method, which matters on the pivot critical path.
 __device__ __forceinline__ double2 crecip(double2 d) {
-  if (fabs(d.x) >= fabs(d.y)) {
-    const double r = d.y / d.x;
-    const double den = d.x + d.y * r;
-    return make_double2(1.0 / den, -r / den);
-  } else {
-    const double r = d.x / d.y;
-    const double den = d.x * r + d.y;
-    return make_double2(r / den, -1.0 / den);
-  }
+  int e;
+  frexp(fmax(fabs(d.x), fabs(d.y)), &e);
+  const double x = ldexp(d.x, -e), y = ldexp(d.y, -e);
+  const double q = ldexp(1.0 / fma(x, x, y * y), -e);
+  return make_double2(x * q, -y * q);
 }
 // a / d, Smith's algorithm
 __device__ __forceinline__ double2 cdiv(double2 a, double2 d) {

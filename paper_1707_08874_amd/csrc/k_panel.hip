@@ -35,12 +35,12 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   int32_t* IW = iws + b * iws_stride;
   const int cand = d.p - d.k, nbk = d.nbk, ld = d.ld, k = d.k;
 
-  __shared__ double2 s_prow[kGroup];
-  __shared__ double s_rv[kPanelThreads / 64];
-  __shared__ int s_ri[kPanelThreads / 64];
+  __shared__ double2 s_prow[2][kGroup];
+  __shared__ double s_rv[2][kPanelThreads / 64];
+  __shared__ int s_ri[2][kPanelThreads / 64];
   __shared__ int s_piv[kMaxNB];
-  __shared__ int s_pivot;
   __shared__ int s_flag;
+  __shared__ double2 s_pcol[2][kMaxNB];
   __shared__ double2 s_buf[kMaxNB * kPiLd];
   __shared__ int s_at[kMaxPivotRows];
   __shared__ int s_pos[kMaxPivotRows];
@@ -89,30 +89,32 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
         const int oi = __shfl_xor(bi, off);
         if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
       }
-      if ((tid & 63) == 0) { s_rv[tid >> 6] = best; s_ri[tid >> 6] = bi; }
+      const int par = c & 1;  // double-buffered partials and pivot row: 2 barriers per column
+      if ((tid & 63) == 0) { s_rv[par][tid >> 6] = best; s_ri[par][tid >> 6] = bi; }
       __syncthreads();
+      double bb = s_rv[par][0];
+      int pr = s_ri[par][0];
+#pragma unroll
+      for (int w = 1; w < kPanelThreads / 64; ++w) {
+        const double v = s_rv[par][w];
+        const int iw = s_ri[par][w];
+        if (v > bb || (v == bb && iw < pr)) { bb = v; pr = iw; }
+      }
+      if (pr < 0 || pr >= cand) { pr = 0; bb = -1.0; }  // keeps every index in range
       if (tid == 0) {
-        double bb = s_rv[0];
-        int ii = s_ri[0];
-        for (int w = 1; w < kPanelThreads / 64; ++w)
-          if (s_rv[w] > bb || (s_rv[w] == bb && s_ri[w] < ii)) { bb = s_rv[w]; ii = s_ri[w]; }
-        if (ii < 0 || ii >= cand) { ii = 0; bb = -1.0; }  // keeps every index in range
-        s_pivot = ii;
-        s_piv[g0 + c] = ii;
+        s_piv[g0 + c] = pr;
         if (!(bb > 0.0) || !isfinite(bb)) s_flag = 1;
       }
-      __syncthreads();
-      const int pr = s_pivot;
 #pragma unroll
       for (int j = 0; j < RPT; ++j) {
         if (tid + j * kPanelThreads == pr) {
 #pragma unroll
-          for (int cc = 0; cc < kGroup; ++cc) s_prow[cc] = cur[j][cc];
+          for (int cc = 0; cc < kGroup; ++cc) s_prow[par][cc] = cur[j][cc];
           used[j] = true;
         }
       }
       __syncthreads();
-      double2 dp = s_prow[c];
+      double2 dp = s_prow[par][c];
       if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) dp = make_double2(1.0, 0.0);
       const double2 invd = crecip(dp);
 #pragma unroll
@@ -127,7 +129,7 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
 #pragma unroll
           for (int cc = 0; cc < kGroup; ++cc) {
             if (cc == c) cur[j][cc] = make_double2(-fi.x, -fi.y);
-            else cur[j][cc] = cfms(cur[j][cc], fi, s_prow[cc]);
+            else cur[j][cc] = cfms(cur[j][cc], fi, s_prow[par][cc]);
           }
         }
       }
@@ -172,55 +174,59 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
     }
   }
 
-  // ---- phase 2: Pi^{-1} by Gauss-Jordan in LDS (rows already in pivot order)
+  // ---- phase 2: Pi^{-1} by Gauss-Jordan without pivoting (rows already in pivot order).
+  // Thread (t, cg) = (tid / 8, tid % 8) keeps entries (t, 8cg .. 8cg+7) in registers; per
+  // column the pivot row and the pivot column go through LDS (double-buffered), one
+  // barrier per column.
   __syncthreads();
-  constexpr int kPer = (kMaxNB * kMaxNB + kPanelThreads - 1) / kPanelThreads;
   {
-    double2 v[kPer];
+    const int t = tid >> 3, cg = tid & 7;
+    const bool live = t < nbk;
+    double2 v[8];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kPanelThreads;
-      v[q] = e < nbk * nbk ? Xp[(int64_t)s_piv[e / nbk] * ld + e % nbk] : make_double2(0.0, 0.0);
+    for (int q = 0; q < 8; ++q) {
+      const int cc = cg * 8 + q;
+      v[q] = (live && cc < nbk) ? Xp[(int64_t)s_piv[t] * ld + cc] : make_double2(0.0, 0.0);
     }
+    for (int c = 0; c < nbk; ++c) {
+      const int par = c & 1;
+      if (live && t == c) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kPanelThreads;
-      if (e < nbk * nbk) s_buf[(e / nbk) * kPiLd + e % nbk] = v[q];
-    }
-  }
-  __syncthreads();
-  for (int c = 0; c < nbk; ++c) {
-    double2 dp = s_buf[c * kPiLd + c];
-    if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) {
-      if (tid == 0) s_flag = 1;
-      dp = make_double2(1.0, 0.0);
-    }
-    const double2 invd = crecip(dp);
-    double2 nv[kPer];
+        for (int q = 0; q < 8; ++q) s_buf[par * kPiLd + cg * 8 + q] = v[q];
+      }
+      if (live && (c >> 3) == cg) {
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kPanelThreads;
-      if (e < nbk * nbk) {
-        const int t = e / nbk, cc = e % nbk;
-        const double2 a = s_buf[t * kPiLd + cc];
+        for (int q = 0; q < 8; ++q)
+          if (q == (c & 7)) s_pcol[par][t] = v[q];
+      }
+      __syncthreads();
+      double2 dp = s_buf[par * kPiLd + c];
+      if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) {
+        if (tid == 0) s_flag = 1;
+        dp = make_double2(1.0, 0.0);
+      }
+      const double2 invd = crecip(dp);
+      if (live) {
         if (t == c) {
-          nv[q] = (cc == c) ? invd : cmul(a, invd);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = (cg * 8 + q == c) ? invd : cmul(v[q], invd);
         } else {
-          const double2 fi = cmul(s_buf[t * kPiLd + c], invd);
-          nv[q] = (cc == c) ? make_double2(-fi.x, -fi.y) : cfms(a, fi, s_buf[c * kPiLd + cc]);
+          const double2 fi = cmul(s_pcol[par][t], invd);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int cc = cg * 8 + q;
+            v[q] = (cc == c) ? make_double2(-fi.x, -fi.y) : cfms(v[q], fi, s_buf[par * kPiLd + cc]);
+          }
         }
       }
     }
-    __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int e = tid + q * kPanelThreads;
-      if (e < nbk * nbk) s_buf[(e / nbk) * kPiLd + (e % nbk)] = nv[q];
+    for (int q = 0; q < 8; ++q) {
+      const int cc = cg * 8 + q;
+      if (live && cc < nbk) Pinv[t * nbk + cc] = v[q];
     }
-    __syncthreads();
   }
-  for (int e = tid; e < nbk * nbk; e += kPanelThreads)
-    Pinv[e] = s_buf[(e / nbk) * kPiLd + (e % nbk)];
+  __syncthreads();
 
   // ---- pivot list, row map of this step, equation ids of the pivot rows
   if (tid < nbk) IW[d.piv_off + tid] = k + s_piv[tid];
