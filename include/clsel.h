@@ -62,6 +62,7 @@ typedef struct {
   int32_t leaf_sites;     /* nested dissection stops at boxes of <= this many sites (default 4) */
   int32_t max_pivot_rows; /* separators with more rows are split into a chain (<= 1536, default 1024) */
   int32_t nb;             /* block width of the frontal Gauss-Jordan sweep (1..64, default 64) */
+  int32_t time_cuts;      /* 1: separators may cut the time direction; 0 (default): never */
 } cl_plan_opts;
 
 typedef struct {
@@ -128,6 +129,9 @@ int cl_status(cl_batch batch, int32_t* per_config_host);
  * resets the counters. */
 int cl_batch_profile(cl_batch batch, int32_t enable);
 int cl_batch_profile_read(cl_batch batch, double* gemm_ms, double* gemm_flops, int64_t* launches);
+/* Non-blocking: 1 if all work enqueued by the batch's last call has finished, 0 if
+ * it is still running, negative on error. */
+int cl_batch_query(cl_batch batch);
 /* Waits for all work of the batch. */
 int cl_batch_sync(cl_batch batch);
 void cl_batch_destroy(cl_batch batch);

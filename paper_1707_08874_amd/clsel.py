@@ -30,7 +30,7 @@ class ClselError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf_sites", ctypes.c_int32), ("max_pivot_rows", ctypes.c_int32),
-                ("nb", ctypes.c_int32)]
+                ("nb", ctypes.c_int32), ("time_cuts", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -49,7 +49,7 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_plan_destroy", "cl_batch_create", "cl_batch_set_active", "cl_batch_use_graph",
            "cl_factor", "cl_selinv", "cl_drift", "cl_selected", "cl_run", "cl_status",
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
-           "cl_batch_profile", "cl_batch_profile_read"]
+           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_query"]
 
 
 def lib():
@@ -83,6 +83,7 @@ def lib():
         "cl_last_error": (ctypes.c_char_p, []),
         "cl_batch_profile": (ctypes.c_int, [vp, ctypes.c_int32]),
         "cl_batch_profile_read": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "cl_batch_query": (ctypes.c_int, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -105,11 +106,12 @@ def _dims(dims):
 class Plan:
     """Symbolic analysis of one lattice shape (cl_symbolic_ex)."""
 
-    def __init__(self, dims, leaf_sites: int = 0, max_pivot_rows: int = 0, nb: int = 0):
+    def __init__(self, dims, leaf_sites: int = 0, max_pivot_rows: int = 0, nb: int = 0,
+                 time_cuts: bool = False):
         L = lib()
         self.dims = tuple(int(v) for v in dims)
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(leaf_sites, max_pivot_rows, nb)
+        opts = PlanOpts(leaf_sites, max_pivot_rows, nb, 1 if time_cuts else 0)
         _check(L.cl_symbolic_ex(_dims(dims), ctypes.byref(opts), ctypes.byref(self._h)))
 
     def info(self) -> dict:
@@ -237,6 +239,13 @@ class Batch:
 
     def sync(self):
         _check(lib().cl_batch_sync(self._h))
+
+    def done(self) -> bool:
+        """True when the work of the last call has finished (does not block)."""
+        rc = lib().cl_batch_query(self._h)
+        if rc < 0:
+            _check(rc)
+        return rc == 1
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

@@ -46,6 +46,7 @@ int dissect(const Box& b, const int L[4], const PlanOptions& opt, std::vector<Se
   int64_t best_sep = std::numeric_limits<int64_t>::max();
   if (vol > opt.leaf_sites) {
     for (int d = 0; d < 4; ++d) {
+      if (d == 3 && !opt.time_cuts) continue;
       int64_t sep;
       if (b.periodic[d]) {
         if (b.len[d] < 4) continue;

@@ -22,6 +22,7 @@ struct PlanOptions {
   int leaf_sites = 4;       // boxes with at most this many sites become leaves
   int max_pivot_rows = 1024;  // cap on p (rows) per supernode; larger separators are chunked
   int nb = 64;              // block width of the frontal Gauss-Jordan sweep
+  int time_cuts = 0;        // 0: separators never cut the time direction, 1: allowed
 };
 
 struct Front {

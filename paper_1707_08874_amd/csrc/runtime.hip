@@ -615,6 +615,7 @@ int cl_symbolic_ex(const int32_t dims[4], const cl_plan_opts* opts, cl_plan* out
     if (opts->leaf_sites > 0) o.leaf_sites = opts->leaf_sites;
     if (opts->max_pivot_rows > 0) o.max_pivot_rows = opts->max_pivot_rows;
     if (opts->nb > 0) o.nb = opts->nb;
+    o.time_cuts = opts->time_cuts != 0;
   }
   if (o.max_pivot_rows > clsel::kMaxPivotRows || o.max_pivot_rows < 3)
     return fail(CL_EINVAL, "max_pivot_rows must be in [3, 1536]");
@@ -866,6 +867,15 @@ int cl_status(cl_batch b, int32_t* out) {
   HIPCHK(hipStreamSynchronize(b->st));
   HIPCHK(hipMemcpy(out, b->status, sizeof(int32_t) * b->active, hipMemcpyDeviceToHost));
   return 0;
+}
+
+int cl_batch_query(cl_batch b) {
+  if (!b) return fail(CL_EINVAL, "null batch");
+  HIPCHK(hipSetDevice(b->device));
+  const hipError_t e = hipEventQuery(b->ev_out);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return fail(CL_EHIP, std::string("hipEventQuery: ") + hipGetErrorString(e));
 }
 
 int cl_batch_sync(cl_batch b) {

@@ -103,3 +103,20 @@ def pure_gauge_blocks(dims, m, mu, g):
         out[:, 1 + nu] = z[:, 1 + nu, None, None] * (g @ ginv[up])
         out[:, 5 + nu] = z[:, 5 + nu, None, None] * (g @ ginv[dn])
     return out
+
+
+def kappa1_bound_free(dims, m, mu):
+    """Upper bound of the 1-norm condition number of the free D: ||D||_1 is exact
+    (m + 3 + cosh(mu) per column) and ||D^{-1}||_1 = ||(m - H) G||_1 <= ||m - H||_1 ||G||_1
+    with ||m - H||_1 = ||D||_1 and ||G||_1 = sum_d |G(d)| (G is a convolution)."""
+    L = [int(v) for v in dims]
+    d1 = m + 3.0 + np.cosh(mu)
+    g = _green_table(L, m, mu)
+    return float(d1 * d1 * np.abs(g).sum())
+
+
+def kappa1_bound_pure_gauge(dims, m, mu, g):
+    """Bound for D = G D_free G^{-1}: kappa_1 <= (max_x ||g_x||_1 ||g_x^{-1}||_1)^2 kappa_1(D_free)."""
+    gi = np.linalg.inv(g)
+    c = (np.abs(g).sum(axis=1).max(axis=1) * np.abs(gi).sum(axis=1).max(axis=1)).max()
+    return float(c * c * kappa1_bound_free(dims, m, mu))

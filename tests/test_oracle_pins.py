@@ -14,6 +14,8 @@ import oracle
 from oracle import staggered, selinv
 from paper_1707_08874_amd.inputs import gen_links, unit_links, pure_gauge_links
 from free_field import free_blocks, pure_gauge_blocks
+from properties import gauss_law_violation as _gauss_law_violation
+from properties import diag_identity_violation as _diag_identity_violation
 
 DIMS = (4, 4, 4, 4)
 M, MU = 0.05, 0.25
@@ -51,43 +53,6 @@ def _logdet_ratio(D, D0_sign, D0_log):
     s, l = np.linalg.slogdet(D)
     ph = np.angle(s / D0_sign)
     return (l - D0_log) + 1j * ph
-
-
-def _gauss_law_violation(K, U, dims):
-    """max over sites of |traceless part of sum_nu [M_{x,nu} - U^{-1} M_{x-nu,nu} U]|,
-    with M reconstructed from K as 1/2 sum_b K_b lambda_b (tr(l_a l_b) = 2 delta)."""
-    lam = selinv.gell_mann()
-    Mt = 0.5 * np.einsum("vnb,bij->vnij", K, lam)
-    _, bwd, _ = staggered.hop_tables(dims)
-    V = U.shape[0]
-    acc = np.zeros((V, 3, 3), dtype=np.complex128)
-    for nu in range(4):
-        y = bwd[:, nu]
-        Uy = U[y, nu]
-        acc += Mt[:, nu] - np.linalg.inv(Uy) @ Mt[y, nu] @ Uy
-    tr = np.trace(acc, axis1=1, axis2=2) / 3
-    acc -= tr[:, None, None] * np.eye(3)
-    return np.abs(acc).max() / np.abs(K).max()
-
-
-def _diag_identity_violation(blocks, U, dims, m, mu):
-    """max_x || sum_y D_{x,y} Z_{y,x} - 1 || using only selected blocks."""
-    fwd, bwd, sign = staggered.hop_tables(dims)
-    eta = staggered.eta_phases(dims)
-    V = U.shape[0]
-    emu = np.ones(4)
-    emu[3] = np.exp(mu)
-    Uinv = np.linalg.inv(U)
-    acc = m * blocks[:, 0].copy()
-    for nu in range(4):
-        # D_{x,x+nu} Z_{x+nu,x}: Z_{x+nu,x} is slot 5+nu of site x+nu
-        cp = 0.5 * eta[:, nu] * sign[:, nu] * emu[nu]
-        acc += cp[:, None, None] * U[:, nu] @ blocks[fwd[:, nu], 5 + nu]
-        # D_{x,x-nu} = -c-(x-nu) U_{x-nu,nu}^{-1}; Z_{x-nu,x} is slot 1+nu of site x-nu
-        y = bwd[:, nu]
-        cm = 0.5 * eta[y, nu] * sign[y, nu] / emu[nu]
-        acc += -cm[:, None, None] * Uinv[y, nu] @ blocks[y, 1 + nu]
-    return np.abs(acc - np.eye(3)).max()
 
 
 # ---------------------------------------------------------------- pins
