@@ -115,6 +115,12 @@ int cl_selinv(cl_batch batch);
 int cl_drift(cl_batch batch, void* out_dev);
 /* Selected blocks [B][V][9][3][3] complex128 into out_dev (device). Enqueues only. */
 int cl_selected(cl_batch batch, void* out_dev);
+/* Fermionic observables from the selected blocks (Sec. 3: like the drift they need
+ * only entries of D^{-1} where D is nonzero): out_dev (device) receives [B][2]
+ * complex128 = { (1/V) tr D^{-1}  (chiral condensate, d/dm log det D / V),
+ *                (1/V) tr(D^{-1} dD/dmu)  (quark number density, d/dmu log det D / V) }.
+ * Deterministic reduction. Enqueues only; needs cl_selinv first. */
+int cl_observables(cl_batch batch, void* out_dev);
 /* cl_factor + cl_selinv + cl_selected + cl_drift in one call; replayed from a
  * HIP graph when enabled. Either output pointer may be NULL. */
 int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host,

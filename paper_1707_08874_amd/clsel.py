@@ -49,7 +49,7 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_plan_destroy", "cl_batch_create", "cl_batch_set_active", "cl_batch_use_graph",
            "cl_factor", "cl_selinv", "cl_drift", "cl_selected", "cl_run", "cl_status",
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
-           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_query"]
+           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_query", "cl_observables"]
 
 
 def lib():
@@ -84,6 +84,7 @@ def lib():
         "cl_batch_profile": (ctypes.c_int, [vp, ctypes.c_int32]),
         "cl_batch_profile_read": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
         "cl_batch_query": (ctypes.c_int, [vp]),
+        "cl_observables": (ctypes.c_int, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -209,6 +210,12 @@ class Batch:
     def drift(self, out=None):
         out = self._alloc((self.active, self.V, 4, 8)) if out is None else out
         _check(lib().cl_drift(self._h, _dev_ptr(out)))
+        return out
+
+    def observables(self, out=None):
+        """[B][2] complex128: (1/V) tr D^{-1} and (1/V) tr(D^{-1} dD/dmu)."""
+        out = self._alloc((self.active, 2)) if out is None else out
+        _check(lib().cl_observables(self._h, _dev_ptr(out)))
         return out
 
     def run(self, links, m, mu, selected_out=None, drift_out=None, want_selected=True):

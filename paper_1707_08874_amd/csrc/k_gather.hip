@@ -101,4 +101,57 @@ k_drift(const double2* __restrict__ sel, const double2* __restrict__ links,
   o[7] = cscale(make_double2(m00.x + m11.x - 2.0 * m22.x, m00.y + m11.y - 2.0 * m22.y), is3);
 }
 
+// Fermionic observables from the selected blocks (the paper notes they need only the
+// entries of D^{-1} where D is nonzero; plotted in Figs. 4 and 6), as volume-normalised
+// derivatives of log det D:
+//   sigma = (1/V) sum_x tr Z_{x,x}                       (d/dm)
+//   n     = (1/V) sum_x [tr(Z_{x+t,x} D_{x,x+t}) - tr(Z_{x,x+t} D_{x+t,x})]   (d/dmu)
+// One work-group per configuration; each thread sums a fixed set of sites, then a
+// wave-shuffle and an LDS stage combine the partials in a fixed order (deterministic).
+__global__ void __launch_bounds__(256)
+k_observables(const double2* __restrict__ sel, const double2* __restrict__ links,
+              const double2* __restrict__ linv, const double* __restrict__ muvals, LatticeDims dims,
+              int64_t V, double2* __restrict__ out) {
+  const int b = blockIdx.x;
+  const double mu = muvals[b];
+  const double emu = exp(mu), emu_inv = exp(-mu);
+  double2 s = make_double2(0.0, 0.0), n = make_double2(0.0, 0.0);
+  for (int64_t x = threadIdx.x; x < V; x += blockDim.x) {
+    const double2* Zx = sel + ((int64_t)b * V + x) * 81;
+    s = cadd(s, cadd(cadd(Zx[0], Zx[4]), Zx[8]));
+    int c[4];
+    dcoords(x, dims, c);
+    int cy[4] = {c[0], c[1], c[2], c[3]};
+    cy[3] = (c[3] + 1) % dims.L[3];
+    const int64_t y = dsite(cy, dims);
+    const double cp = dcplus(c, 3, dims, emu);      // D_{x,x+t} = cp U
+    const double cm = dcminus(c, 3, dims, emu_inv); // D_{x+t,x} = -cm U^{-1}
+    const double2* U = links + (((int64_t)b * V + x) * 4 + 3) * 9;
+    const double2* Ui = linv + (((int64_t)b * V + x) * 4 + 3) * 9;
+    const double2* P = Zx + 4 * 9;                                   // Z_{x,x+t}
+    const double2* Q = sel + ((int64_t)b * V + y) * 81 + 8 * 9;      // Z_{x+t,x}
+    double2 tq = make_double2(0.0, 0.0), tp = make_double2(0.0, 0.0);
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) {
+        tq = cfma(tq, Q[i * 3 + k], U[k * 3 + i]);   // tr(Q U)
+        tp = cfma(tp, P[i * 3 + k], Ui[k * 3 + i]);  // tr(P U^{-1})
+      }
+    n = cadd(n, cadd(cscale(tq, cp), cscale(tp, cm)));
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s.x += __shfl_xor(s.x, off); s.y += __shfl_xor(s.y, off);
+    n.x += __shfl_xor(n.x, off); n.y += __shfl_xor(n.y, off);
+  }
+  __shared__ double2 part[2][4];
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { part[0][w] = s; part[1][w] = n; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 S = part[0][0], Nn = part[1][0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) { S = cadd(S, part[0][k]); Nn = cadd(Nn, part[1][k]); }
+    out[2 * b] = cscale(S, 1.0 / (double)V);
+    out[2 * b + 1] = cscale(Nn, 1.0 / (double)V);
+  }
+}
+
 }  // namespace clsel

@@ -30,6 +30,9 @@ __global__ void k_drift(const double2* sel, const double2* links, const double2*
                         const double* muvals, LatticeDims dims, int64_t V, int nbatch,
                         double2* out);
 
+__global__ void k_observables(const double2* sel, const double2* links, const double2* linv,
+                              const double* muvals, LatticeDims dims, int64_t V, double2* out);
+
 void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs,
                   const double2* fronts, int64_t cfg_stride, double2* ws, int64_t ws_stride,
                   int32_t* iws, int64_t iws_stride, int32_t* status);

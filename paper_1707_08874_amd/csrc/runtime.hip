@@ -797,6 +797,18 @@ int cl_drift(cl_batch b, void* out) {
   return end(b);
 }
 
+int cl_observables(cl_batch b, void* out) {
+  if (!b || !out) return fail(CL_EINVAL, "null argument");
+  if (b->state < 2) return fail(CL_EORDER, "cl_observables before cl_selinv");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  const clsel::Plan& P = b->plan->P;
+  hipLaunchKernelGGL(clsel::k_observables, dim3(b->active), dim3(256), 0, b->st, b->sel, b->links,
+                     b->linv, b->params + b->cap, ldims(P), P.V, (double2*)out);
+  HIPCHK(hipGetLastError());
+  return end(b);
+}
+
 int cl_run(cl_batch b, const void* links_dev, const double* m_host, const double* mu_host,
            void* sel_out, void* drift_out) {
   if (!b || !links_dev || !m_host || !mu_host) return fail(CL_EINVAL, "null argument");

@@ -25,7 +25,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-from . import clsel
+from . import autotune, clsel
 from .inputs import gen_links, volume
 
 DEFAULT_MIX = (((4, 4, 4, 4), 0.3), ((6, 6, 6, 6), 0.3), ((8, 8, 8, 4), 0.3), ((12, 12, 12, 6), 0.1))
@@ -99,7 +99,10 @@ class Server:
     def plan(self, dims) -> clsel.Plan:
         dims = tuple(int(v) for v in dims)
         if dims not in self.plans:
-            self.plans[dims] = clsel.Plan(dims, **self.plan_opts.get(dims, {}))
+            opts = self.plan_opts.get(dims)
+            if opts is None:
+                opts = autotune.options(dims, 1)
+            self.plans[dims] = clsel.Plan(dims, **opts)
         return self.plans[dims]
 
     def capacity(self, dims) -> int:

@@ -163,3 +163,24 @@ def test_call_order_errors(torch_cuda):
         batch.drift()
     assert e.value.code == clsel.CL_EORDER
     batch.close()
+
+
+def test_observables_match_oracle(torch_cuda):
+    """Chiral condensate and number density from the GPU's selected blocks against the
+    oracle's (which are pinned to d/dm and d/dmu of log det D)."""
+    torch = torch_cuda
+    dims = (4, 4, 4, 6)
+    U = gen_batch(dims, [21, 22])
+    m = np.array([0.05, 0.1])
+    mu = np.array([0.25, 0.0])
+    plan = clsel.Plan(dims)
+    batch = clsel.Batch(plan, 2)
+    batch.run(torch.from_numpy(U).to("cuda"), m, mu)
+    obs = batch.observables().cpu().numpy()
+    batch.close()
+    for b in range(2):
+        ref_sel, _, tol = _oracle(U[b], dims, m[b], mu[b])
+        sig = oracle.chiral_condensate(ref_sel)
+        n = oracle.number_density(ref_sel, U[b], dims, m[b], mu[b])
+        assert abs(obs[b, 0] - sig) <= tol * abs(sig), (b, obs[b, 0], sig)
+        assert abs(obs[b, 1] - n) <= tol * max(abs(n), abs(sig)), (b, obs[b, 1], n)
