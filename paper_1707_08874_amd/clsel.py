@@ -30,7 +30,7 @@ class ClselError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf_sites", ctypes.c_int32), ("max_pivot_rows", ctypes.c_int32),
-                ("nb", ctypes.c_int32), ("time_cuts", ctypes.c_int32)]
+                ("nb", ctypes.c_int32), ("time_cuts", ctypes.c_int32), ("gemm_tile", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -108,11 +108,11 @@ class Plan:
     """Symbolic analysis of one lattice shape (cl_symbolic_ex)."""
 
     def __init__(self, dims, leaf_sites: int = 0, max_pivot_rows: int = 0, nb: int = 0,
-                 time_cuts: bool = False):
+                 time_cuts: bool = False, gemm_tile: int = 0):
         L = lib()
         self.dims = tuple(int(v) for v in dims)
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(leaf_sites, max_pivot_rows, nb, 1 if time_cuts else 0)
+        opts = PlanOpts(leaf_sites, max_pivot_rows, nb, 1 if time_cuts else 0, gemm_tile)
         _check(L.cl_symbolic_ex(_dims(dims), ctypes.byref(opts), ctypes.byref(self._h)))
 
     def info(self) -> dict:

@@ -43,14 +43,20 @@ __global__ void k_link_inverse(const double2* __restrict__ links, double2* __res
   o[6] = cdiv(c02, det); o[7] = cdiv(c12, det); o[8] = cdiv(c22, det);
 }
 
-// Entry D_{(x,a),(y,b)} of the staggered operator.
-__device__ double2 dirac_entry(int64_t x, int a, int64_t y, int b, const double2* __restrict__ U,
+// Entry D_{(x,a),(y,b)} of the staggered operator (site indices fit in 32 bits).
+__device__ double2 dirac_entry(int x, int a, int y, int b, const double2* __restrict__ U,
                                const double2* __restrict__ Uinv, double m, double emu,
                                double emu_inv, const LatticeDims& dims) {
   if (x == y) return make_double2(a == b ? m : 0.0, 0.0);
   int cx[4], cy[4];
-  dcoords(x, dims, cx);
-  dcoords(y, dims, cy);
+  {
+    int rx = x, ry = y;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      cx[k] = rx % dims.L[k]; rx /= dims.L[k];
+      cy[k] = ry % dims.L[k]; ry /= dims.L[k];
+    }
+  }
   int ndiff = 0, nu = -1;
   for (int k = 0; k < 4; ++k)
     if (cx[k] != cy[k]) { ++ndiff; nu = k; }
@@ -58,11 +64,11 @@ __device__ double2 dirac_entry(int64_t x, int a, int64_t y, int b, const double2
   const int L = dims.L[nu];
   if (cy[nu] == (cx[nu] + 1) % L) {  // y = x + nu: +c+(x,nu) U_{x,nu}
     const double cp = dcplus(cx, nu, dims, emu);
-    return cscale(U[(x * 4 + nu) * 9 + a * 3 + b], cp);
+    return cscale(U[((int64_t)x * 4 + nu) * 9 + a * 3 + b], cp);
   }
   if (cx[nu] == (cy[nu] + 1) % L) {  // x = y + nu: -c-(y,nu) U_{y,nu}^{-1}
     const double cm = dcminus(cy, nu, dims, emu_inv);
-    return cscale(Uinv[(y * 4 + nu) * 9 + a * 3 + b], -cm);
+    return cscale(Uinv[((int64_t)y * 4 + nu) * 9 + a * 3 + b], -cm);
   }
   return make_double2(0.0, 0.0);
 }
@@ -84,10 +90,10 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     if (descs[mid].blk_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
   }
   const AsmDesc& d = descs[lo];
-  const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
-  const int64_t HH = (int64_t)d.H * d.H;
-  if (e >= HH) return;
-  const int I = (int)(e / d.H), J = (int)(e % d.H);
+  // H <= 16383, so H*H and every element index fit in 32 bits (cheap division)
+  const int e = (int)((int64_t)blockIdx.x - d.blk_start) * 256 + (int)threadIdx.x;
+  if (e >= d.H * d.H) return;
+  const int I = e / d.H, J = e - (e / d.H) * d.H;
   double2* F = fronts + b * cfg_stride;
   double2 v = make_double2(0.0, 0.0);
   for (int c = 0; c < d.nchild; ++c) {
@@ -99,8 +105,8 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     }
   }
   if (I < d.p || J < d.p) {
-    const int64_t x = front_sites[d.site_off + I / 3];
-    const int64_t y = front_sites[d.site_off + J / 3];
+    const int x = front_sites[d.site_off + I / 3];
+    const int y = front_sites[d.site_off + J / 3];
     const double mu = muvals[b];
     v = cadd(v, dirac_entry(x, I % 3, y, J % 3, links + b * link_cfg_stride,
                             linv + b * link_cfg_stride, mvals[b], exp(mu), exp(-mu), dims));

@@ -18,9 +18,9 @@ k_gather_zss(const GatherDesc* __restrict__ descs, int ndesc, double2* __restric
     if (descs[mid].blk_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
   }
   const GatherDesc& d = descs[lo];
-  const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
-  if (e >= (int64_t)d.s * d.s) return;
-  const int a = (int)(e / d.s), c = (int)(e % d.s);
+  const int e = (int)((int64_t)blockIdx.x - d.blk_start) * 256 + (int)threadIdx.x;
+  if (e >= d.s * d.s) return;
+  const int a = e / d.s, c = e - (e / d.s) * d.s;
   double2* F = fronts + b * cfg_stride;
   const int ra = rel_maps[d.rel_off + a], rc = rel_maps[d.rel_off + c];
   F[d.z_off + (int64_t)(d.p + a) * d.ld + d.p + c] = F[d.par_off + (int64_t)ra * d.par_ld + rc];

@@ -2,8 +2,8 @@
 //
 // A complex product C = A*B is four real products: Re C = Ar*Br - Ai*Bi,
 // Im C = Ar*Bi + Ai*Br (no 3M trick, so rounding matches the plain 4-multiply form).
-// Each work-group computes a 64 x 64 complex tile with 4 waves (2 x 2), each wave a
-// 32 x 32 tile made of 2 x 2 MFMA tiles of 16 x 16 with two FP64 accumulators
+// Each work-group computes a BM x BN complex tile (64 x 64 or 128 x 128) with 4 waves
+// (2 x 2), each wave a (BM/2) x (BN/2) tile made of TM x TN MFMA tiles of 16 x 16 with two FP64 accumulators
 // (real part fed by Ar*Br and (-Ai)*Bi, imaginary part by Ar*Bi and Ai*Br). K advances
 // 16 complex per stage through LDS, real and imaginary planes stored k-major so the
 // MFMA operand reads are contiguous; the next stage's global loads are issued into
@@ -26,7 +26,7 @@ namespace clsel {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BK = 16;
 constexpr int kGemmThreads = 256;
 constexpr int kXcds = 8;
 
@@ -46,16 +46,15 @@ __device__ __forceinline__ double2* pool_ptr(const GemmCtx& g, int b, int pool) 
 }
 
 // Per-thread operand sources, fixed for the whole K loop.
-template <int MODE>
+template <int MODE, int RA>
 struct Operands {
-  const double2* arow[4];  // A rows handled by this thread (nullptr: zero or special)
-  int ai[4];               // A row index (global)
-  const double2* bbase;    // B base
-  int bcol;                // B column handled by this thread
+  const double2* arow[RA];  // A rows handled by this thread (nullptr: zero or special)
+  int ai[RA];               // A row index (global)
+  const double2* bbase;     // B base
 };
 
-template <int MODE>
-__device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE>& o, int r, int t) {
+template <int MODE, int RA>
+__device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE, RA>& o, int r, int t) {
   const double2 z = make_double2(0.0, 0.0);
   if (t >= d.K || o.ai[r] >= d.M) return z;
   if (MODE == 2) {
@@ -71,9 +70,11 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
   return x * q + min(x, r) + local;
 }
 
-template <int MODE>
-__global__ void __launch_bounds__(kGemmThreads, 2)
+template <int MODE, int TM, int TN>
+__global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : 2)
 k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  constexpr int RA = BM / 16, RB = BN / 16;  // complex loads per thread per stage
   const int b = blockIdx.y;
   const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
   int lo = 0, hi = ndesc - 1;
@@ -88,22 +89,24 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 
   __shared__ double As[2][BK][BM + 1];
   __shared__ double Bs[2][BK][BN + 1];
+  static_assert(BN <= kGemmThreads && kGemmThreads % BN == 0, "B load mapping");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, l4 = lane >> 4;
   const int a_kk = tid & 15;          // A loads: rows (tid>>4) + 16r, k = tid & 15
-  const int b_n = tid & 63;           // B loads: col tid & 63, k rows (tid>>6) + 4r
-  const int b_kk0 = tid >> 6;
+  const int b_n = tid % BN;           // B loads: col tid % BN, k rows tid / BN + (256/BN) r
+  const int b_kk0 = tid / BN;
+  constexpr int b_kstep = kGemmThreads / BN;
 
   double2* F = g.fronts + b * g.cfg_stride;
   double2* W = g.ws + b * g.ws_stride;
   const int32_t* IW = g.iws + b * g.iws_stride;
 
-  Operands<MODE> o;
+  Operands<MODE, RA> o;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
+  for (int r = 0; r < RA; ++r) {
     const int i = row0 + (tid >> 4) + 16 * r;
     o.ai[r] = i;
     o.arow[r] = nullptr;
@@ -113,14 +116,14 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       else o.arow[r] = F + d.x_off + (int64_t)IW[d.rmap_off + i] * d.ld + d.k;
     }
   }
-  o.bcol = col0 + b_n;
+  const int bcol = col0 + b_n;
   if (MODE == 0) o.bbase = pool_ptr(g, b, d.b_pool) + d.b_off;
   else if (MODE == 1) o.bbase = F + d.x_off;
   else o.bbase = W + d.rt_off;
 
   auto ld_b = [&](int t) -> double2 {
     const double2 z = make_double2(0.0, 0.0);
-    const int j = o.bcol;
+    const int j = bcol;
     if (t >= d.K || j >= d.N) return z;
     if (MODE == 0) return o.bbase[(int64_t)t * d.ldb + j];
     if (MODE == 1) {
@@ -130,36 +133,35 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     return o.bbase[(int64_t)t * d.N + j];
   };
 
-  d4 cr[2][2], ci[2][2];
+  d4 cr[TM][TN], ci[TM][TN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < TN; ++j) {
       cr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       ci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-  double2 pa[4], pb[4];
+  double2 pa[RA], pb[RB];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    pa[r] = ld_a<MODE>(d, o, r, a_kk);
-    pb[r] = ld_b(b_kk0 + 4 * r);
-  }
+  for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, a_kk);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) pb[r] = ld_b(b_kk0 + b_kstep * r);
 
   // mode 2: the old front values that the update is subtracted from, loaded during the
   // last K stage so the loads overlap its MFMAs
-  double2 base[2][2][4];
+  double2 base[TM][TN][4];
   auto load_base = [&]() {
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 32 + i * 16 + 4 * r + l4;
+        const int row = row0 + wm * (BM / 2) + i * 16 + 4 * r + l4;
         const bool rok = row < d.M && !(row >= d.k && row < d.k + d.nbk);
         const double2* xr = rok ? F + d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld : nullptr;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const int col = col0 + wn * 32 + j * 16 + l16;
+        for (int j = 0; j < TN; ++j) {
+          const int col = col0 + wn * (BN / 2) + j * 16 + l16;
           const bool ok = rok && col < d.N && !(col >= d.k && col < d.k + d.nbk);
           base[i][j][r] = ok ? xr[col] : make_double2(0.0, 0.0);
         }
@@ -168,11 +170,14 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 
   auto store_stage = [&]() {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < RA; ++r) {
       const int m = (tid >> 4) + 16 * r;
       As[0][a_kk][m] = pa[r].x;
       As[1][a_kk][m] = pa[r].y;
-      const int kk = b_kk0 + 4 * r;
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int kk = b_kk0 + b_kstep * r;
       Bs[0][kk][b_n] = pb[r].x;
       Bs[1][kk][b_n] = pb[r].y;
     }
@@ -181,29 +186,29 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kk = 4 * k4 + l4;
-      double ar[2], ai[2], nai[2], br[2], bi[2];
+      double ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        ar[i] = As[0][kk][wm * 32 + i * 16 + l16];
-        ai[i] = As[1][kk][wm * 32 + i * 16 + l16];
+      for (int i = 0; i < TM; ++i) {
+        ar[i] = As[0][kk][wm * (BM / 2) + i * 16 + l16];
+        ai[i] = As[1][kk][wm * (BM / 2) + i * 16 + l16];
         nai[i] = -ai[i];
       }
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        br[j] = Bs[0][kk][wn * 32 + j * 16 + l16];
-        bi[j] = Bs[1][kk][wn * 32 + j * 16 + l16];
+      for (int j = 0; j < TN; ++j) {
+        br[j] = Bs[0][kk][wn * (BN / 2) + j * 16 + l16];
+        bi[j] = Bs[1][kk][wn * (BN / 2) + j * 16 + l16];
       }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < TN; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
           ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
         }
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < TN; ++j) {
           cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
           ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
         }
@@ -216,10 +221,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     store_stage();
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      pa[r] = ld_a<MODE>(d, o, r, k0 + BK + a_kk);
-      pb[r] = ld_b(k0 + BK + b_kk0 + 4 * r);
-    }
+    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + BK + a_kk);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + BK + b_kk0 + b_kstep * r);
     mfma_stage();
     __syncthreads();
   }
@@ -230,13 +234,13 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   mfma_stage();
 
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < TM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * 32 + i * 16 + 4 * r + l4;
-        const int col = col0 + wn * 32 + j * 16 + l16;
+        const int row = row0 + wm * (BM / 2) + i * 16 + 4 * r + l4;
+        const int col = col0 + wn * (BN / 2) + j * 16 + l16;
         if (row >= d.M || col >= d.N) continue;
         const double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
         if (MODE == 0) {
@@ -254,15 +258,16 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       }
 }
 
-void launch_gemm(int mode, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
+void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride) {
   GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride};
-  switch (mode) {
-    case 0: hipLaunchKernelGGL(k_gemm<0>, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g); break;
-    case 1: hipLaunchKernelGGL(k_gemm<1>, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g); break;
-    default: hipLaunchKernelGGL(k_gemm<2>, grid, dim3(kGemmThreads), 0, st, descs, ndesc, g); break;
-  }
+  const dim3 blk(kGemmThreads);
+  if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 0 && tile == kTile128x64) hipLaunchKernelGGL((k_gemm<0, 4, 2>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 0) hipLaunchKernelGGL((k_gemm<0, 2, 2>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 1) hipLaunchKernelGGL((k_gemm<1, 2, 2>), grid, blk, 0, st, descs, ndesc, g);
+  else hipLaunchKernelGGL((k_gemm<2, 2, 2>), grid, blk, 0, st, descs, ndesc, g);
 }
 
 }  // namespace clsel

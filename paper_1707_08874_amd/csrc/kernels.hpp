@@ -10,6 +10,8 @@
 namespace clsel {
 
 constexpr int kMaxNB = 64;            // widest Gauss-Jordan block
+// output tiles of the plain (mode 0) GEMMs
+constexpr int kTile64 = 64, kTile128x64 = 12864, kTile128 = 128;
 constexpr int kMaxPivotRows = 1536;   // pivot rows per supernode the panel kernel can hold
 constexpr int32_t kStatusSingular = -4;
 constexpr int32_t kStatusNonFinite = -5;
@@ -36,7 +38,7 @@ __global__ void k_observables(const double2* sel, const double2* links, const do
 void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs,
                   const double2* fronts, int64_t cfg_stride, double2* ws, int64_t ws_stride,
                   int32_t* iws, int64_t iws_stride, int32_t* status);
-void launch_gemm(int mode, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc, double2* fronts,
+void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc, double2* fronts,
                  int64_t cfg_stride, int64_t pool_elems, double2* ws, int64_t ws_stride,
                  const int32_t* iws, int64_t iws_stride);
 

@@ -49,6 +49,7 @@ struct Launch {
   int64_t gridx;
   int rpt;           // panel rows per thread; GEMM mode for GEMM launches
   double flops = 0;  // per configuration: 8*M*N*K summed over the GEMM problems
+  int tile = 64;     // GEMM output tile edge (64 or 128)
 };
 
 struct Layout {
@@ -69,6 +70,30 @@ size_t blob_push(std::vector<char>& blob, const void* p, size_t n) {
 }
 
 inline int64_t cdiv64(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Chooses the output tile of a grouped GEMM launch and numbers its tiles. Larger tiles
+// (128 x 64, 128 x 128) cut operand traffic per flop but drop to one wave per SIMD and
+// measured slower on MI355X, so they are used only when the plan asks for them and every
+// problem of the launch is at least 128 x 128.
+Launch gemm_launch(std::vector<char>& blob, std::vector<clsel::GemmDesc>& g, int mode, int pref) {
+  int tile = clsel::kTile64;
+  if (mode == 0) {
+    bool big = !g.empty();
+    for (const clsel::GemmDesc& d : g) big = big && d.M >= 128 && d.N >= 128;
+    if (big && pref != 0) tile = pref;  // 64 x 64 unless asked: it keeps 3 waves per SIMD
+  }
+  const int tm = tile == clsel::kTile64 ? 64 : 128;
+  const int tn = tile == clsel::kTile128 ? 128 : 64;
+  int64_t t = 0;
+  for (clsel::GemmDesc& d : g) {
+    d.tiles_n = (int)cdiv64(d.N, tn);
+    d.tile_start = t;
+    t += cdiv64(d.M, tm) * d.tiles_n;
+  }
+  Launch l{kGemm, blob_push(blob, g.data(), g.size() * sizeof(g[0])), (int)g.size(), t, mode};
+  l.tile = tile;
+  return l;
+}
 
 void build_layout(const clsel::Plan& P, Layout& L) {
   const int64_t pool = P.pool_elems;
@@ -156,10 +181,8 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       iws_max = std::max(iws_max, iwo);
       L.factor.push_back({kPanel, blob_push(L.blob, pd.data(), pd.size() * sizeof(pd[0])),
                           (int)pd.size(), (int64_t)pd.size(), rpt});
-      L.factor.push_back({kGemm, blob_push(L.blob, g1.data(), g1.size() * sizeof(g1[0])),
-                          (int)g1.size(), t1, 1});
-      L.factor.push_back({kGemm, blob_push(L.blob, g2.data(), g2.size() * sizeof(g2[0])),
-                          (int)g2.size(), t2, 2});
+      L.factor.push_back(gemm_launch(L.blob, g1, 1, 0));
+      L.factor.push_back(gemm_launch(L.blob, g2, 2, 0));
     }
     // update rows of every front of the level, from their assembled values (pool 0)
     // and the swept pivot rows (pool 1):
@@ -191,9 +214,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       sj.tile_start = ts; ts += cdiv64(sj.M, 64) * sj.tiles_n;
       gs.push_back(sj);
     }
-    if (!gs.empty())
-      L.factor.push_back({kGemm, blob_push(L.blob, gs.data(), gs.size() * sizeof(gs[0])),
-                          (int)gs.size(), ts, 0});
+    if (!gs.empty()) L.factor.push_back(gemm_launch(L.blob, gs, 0, P.opt.gemm_tile));
   }
 
   // selected inversion, root level first
@@ -250,10 +271,8 @@ void build_layout(const clsel::Plan& P, Layout& L) {
     if (gd.empty()) continue;
     L.selinv.push_back({kZss, blob_push(L.blob, gd.data(), gd.size() * sizeof(gd[0])),
                         (int)gd.size(), blk, 0});
-    L.selinv.push_back({kGemm, blob_push(L.blob, ga.data(), ga.size() * sizeof(ga[0])),
-                        (int)ga.size(), ta, 0});
-    L.selinv.push_back({kGemm, blob_push(L.blob, gb.data(), gb.size() * sizeof(gb[0])),
-                        (int)gb.size(), tb, 0});
+    L.selinv.push_back(gemm_launch(L.blob, ga, 0, P.opt.gemm_tile));
+    L.selinv.push_back(gemm_launch(L.blob, gb, 0, P.opt.gemm_tile));
   }
   L.ws_elems = std::max<int64_t>(ws_max, 16);
   L.iws_elems = iws_max;
@@ -285,6 +304,7 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
       for (int i = 0; i < l.count; ++i) {
         REQ(d[i].blk_start == blk, "asm block start", d[i].blk_start, blk);
         blk += cdiv64((int64_t)d[i].H * d[i].H, 256);
+        REQ((int64_t)d[i].H * d[i].H < (int64_t(1) << 31), "asm 32-bit element index", d[i].H, 46340);
         REQ(d[i].off + (int64_t)d[i].H * d[i].ld <= pool, "asm front", d[i].off, pool);
         REQ(d[i].joff + (int64_t)d[i].p * d[i].ld <= two, "asm pivot rows", d[i].joff, two);
         REQ(d[i].site_off + d[i].H / 3 <= (int64_t)P.front_sites.size(), "asm sites", d[i].site_off, 0);
@@ -321,9 +341,11 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
       int64_t t = 0;
       for (int i = 0; i < l.count; ++i) {
         const clsel::GemmDesc& g = d[i];
+        const int tm = l.tile == clsel::kTile64 ? 64 : 128, tn = l.tile == clsel::kTile128 ? 128 : 64;
         REQ(g.tile_start == t, "gemm tile start", g.tile_start, t);
-        t += cdiv64(g.M, 64) * g.tiles_n;
-        REQ(g.tiles_n == cdiv64(g.N, 64), "gemm tiles_n", g.tiles_n, cdiv64(g.N, 64));
+        t += cdiv64(g.M, tm) * g.tiles_n;
+        REQ(g.tiles_n == cdiv64(g.N, tn), "gemm tiles_n", g.tiles_n, cdiv64(g.N, tn));
+        REQ(l.tile == clsel::kTile64 || g.mode == 0, "gemm tile", l.tile, 64);
         if (g.mode == 0) {
           auto lim = [&](int pool_id) { return pool_id == clsel::kPoolWs ? L.ws_elems : pool; };
           REQ(g.a_off + (int64_t)(g.M - 1) * g.lda + g.K <= lim(g.a_pool), "gemm A", g.a_off, lim(g.a_pool));
@@ -350,6 +372,7 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
     const clsel::GatherDesc* d = (const clsel::GatherDesc*)(L.blob.data() + l.desc_off);
     for (int i = 0; i < l.count; ++i) {
       const int64_t H = d[i].p + d[i].s;
+      REQ((int64_t)d[i].s * d[i].s < (int64_t(1) << 31), "gather 32-bit element index", d[i].s, 46340);
       REQ(d[i].z_off + H * d[i].ld <= two, "gather front", d[i].z_off, two);
       REQ(d[i].rel_off + d[i].s <= (int64_t)P.rel_maps.size(), "gather rel", d[i].rel_off, 0);
       int64_t mx = 0;
@@ -485,7 +508,7 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
           b->prof_flops.push_back(l.flops * B);
           HIPCHK(hipEventRecord(e0, b->st));
         }
-        clsel::launch_gemm(l.rpt, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
+        clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws,
                            b->L.iws_elems);
         if (b->prof) HIPCHK(hipEventRecord(e1, b->st));
@@ -616,7 +639,11 @@ int cl_symbolic_ex(const int32_t dims[4], const cl_plan_opts* opts, cl_plan* out
     if (opts->max_pivot_rows > 0) o.max_pivot_rows = opts->max_pivot_rows;
     if (opts->nb > 0) o.nb = opts->nb;
     o.time_cuts = opts->time_cuts != 0;
+    o.gemm_tile = opts->gemm_tile;
   }
+  if (o.gemm_tile != 0 && o.gemm_tile != clsel::kTile64 && o.gemm_tile != clsel::kTile128x64 &&
+      o.gemm_tile != clsel::kTile128)
+    return fail(CL_EINVAL, "gemm_tile must be 0, 64, 12864 or 128");
   if (o.max_pivot_rows > clsel::kMaxPivotRows || o.max_pivot_rows < 3)
     return fail(CL_EINVAL, "max_pivot_rows must be in [3, 1536]");
   if (o.nb > clsel::kMaxNB) return fail(CL_EINVAL, "nb must be in [1, 64]");
