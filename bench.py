@@ -5,11 +5,17 @@ inversion, gather of the selected blocks, drift) over one batch of 64 synthetic
 8^3x4 configurations (seeds 0..63, eps ~ U[0.02, 0.3], m = 0.05, mu = 0.25) that
 share one symbolic analysis. Inputs are resident in HBM before the timed region.
 Also reported: the plain single-configuration path (graph replay, B = 1) with its
-p50/p99 latency, the roofline of the complex GEMM kernel (HIP events around every
-launch, algorithmic 8*M*N*K flops), parity of a sampled configuration against the
+p50/p99 latency, the roofline of the dominant kernel, the mode-0 complex GEMM
+(Schur complements and selected-inversion products: HIP events around each of its
+launches, algorithmic 8*M*N*K flops), parity of a sampled configuration against the
 CPU oracle, and the oracle itself timed on the host as the CPU baseline.
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1]
+
+For the two HBM-counter passes: ``--calibrate-copy`` first runs a plain copy kernel
+of known size (torch's elementwise negation, 1 GiB read and 1 GiB written) whose
+counter readings scale the GEMM's, and ``--skip-plain --no-cpu-baseline`` keep the
+run to the batched step.
 """
 import argparse
 import json
@@ -22,6 +28,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
+COPY_BYTES = 1 << 30
+GEMM_KERNEL = "k_gemm<0, 2, 2, 8, 2>"
 
 
 def _blas_threads():
@@ -41,6 +49,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--plain-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     args = ap.parse_args()
@@ -56,6 +66,14 @@ def main():
     from paper_1707_08874_amd.inputs import gen_batch
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
+    if args.calibrate_copy:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"[bench] copy calibration: 3 x {COPY_BYTES} bytes", file=sys.stderr, flush=True)
     t = time.time()
     links = gen_batch(dims, range(B))
     print(f"[bench] generated {B} configs in {time.time() - t:.1f}s", file=sys.stderr, flush=True)
@@ -81,7 +99,7 @@ def main():
     for _ in range(args.warmup):
         batch.run(lt, m, mu, sel, drift)
     torch.cuda.synchronize()
-    batch.profile(True)
+    batch.profile(1)  # mode-0 GEMM launches only
     batch.profile_read()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -90,8 +108,8 @@ def main():
     batch.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    gemm_ms, gemm_flops, launches = batch.profile_read()
-    batch.profile(False)
+    gemm_ms, gemm_flops, gemm_bytes, launches = batch.profile_read()
+    batch.profile(0)
     status = batch.status()
     dt = t1 - t0
     value = B * args.steps / dt
@@ -103,26 +121,31 @@ def main():
 
     # ---- plain path: one configuration, graph replay
     opts_1 = plan_opts(1)
-    plan1 = clsel.Plan(dims, **opts_1)
-    pb = clsel.Batch(plan1, 1)
-    pb.use_graph(True)
-    l1 = lt[:1].contiguous()
-    s1 = torch.empty((1, V, 9, 3, 3), dtype=torch.complex128, device="cuda")
-    d1 = torch.empty((1, V, 4, 8), dtype=torch.complex128, device="cuda")
-    for _ in range(3):
-        pb.run(l1, m, mu, s1, d1)
-    pb.sync()
-    lat = []
-    for _ in range(args.plain_reps):
-        a = time.perf_counter()
-        pb.run(l1, m, mu, s1, d1)
+    plain = None
+    if not args.skip_plain:
+        plan1 = clsel.Plan(dims, **opts_1)
+        pb = clsel.Batch(plan1, 1)
+        pb.use_graph(True)
+        l1 = lt[:1].contiguous()
+        s1 = torch.empty((1, V, 9, 3, 3), dtype=torch.complex128, device="cuda")
+        d1 = torch.empty((1, V, 4, 8), dtype=torch.complex128, device="cuda")
+        for _ in range(3):
+            pb.run(l1, m, mu, s1, d1)
         pb.sync()
-        lat.append(time.perf_counter() - a)
-    lat = np.array(lat)
-    plain_value = 1.0 / lat.mean()
-    plain_dev = float(np.abs(s1[0].cpu().numpy() - sel0).max() / np.abs(sel0).max())
-    pb.close()
-    print(f"[bench] plain: p50 {np.median(lat) * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        lat = []
+        for _ in range(args.plain_reps):
+            a = time.perf_counter()
+            pb.run(l1, m, mu, s1, d1)
+            pb.sync()
+            lat.append(time.perf_counter() - a)
+        lat = np.array(lat)
+        plain = {"value": 1.0 / lat.mean(), "unit": "configs/s",
+                 "p50_ms": float(np.median(lat) * 1e3),
+                 "p99_ms": float(np.quantile(lat, 0.99) * 1e3), "reps": args.plain_reps,
+                 "max_dev_from_batched": float(np.abs(s1[0].cpu().numpy() - sel0).max()
+                                               / np.abs(sel0).max())}
+        pb.close()
+        print(f"[bench] plain: p50 {plain['p50_ms']:.2f} ms", file=sys.stderr, flush=True)
 
     # ---- CPU oracle on one sampled configuration: baseline timing + parity
     cpu = None
@@ -153,6 +176,19 @@ def main():
 
     avg_launch_ms = gemm_ms / max(launches, 1)
     achieved = gemm_flops / max(gemm_ms, 1e-9) / 1e9  # TFLOP/s
+    workload = {"dims": list(dims), "batch": B, "plan": opts_b}
+    traffic, traffic_note = None, "no counter record"
+    rec_path = os.path.join(ROOT, "paper_1707_08874_amd", "traffic.json")
+    if os.path.exists(rec_path):
+        from paper_1707_08874_amd.profsum import source_digest
+        with open(rec_path) as f:
+            rec = json.load(f)
+        if rec.get("source_sha256") != source_digest():
+            traffic_note = "kernel source changed since the counters were taken"
+        elif rec.get("workload") != workload:
+            traffic_note = "counters were taken on another workload"
+        else:
+            traffic, traffic_note = rec["bytes_per_launch"], rec.get("command", "")
     out = {
         "metric": "selected inversions+drift/sec at 8^3x4 c128 (batched vs plain); p50/p99 latency",
         "value": value,
@@ -169,15 +205,17 @@ def main():
         "config": {"workload": f"batched: {B} x 8^3x4 lattices (N=6144 each), seeds 0..{B - 1}, "
                                "eps~U[0.02,0.3], m=0.05, mu=0.25, one shared symbolic analysis",
                    "lattice": "8x8x8x4", "batch": B, "plan_batched": opts_b, "plan_plain": opts_1},
-        "plain": {"value": plain_value, "unit": "configs/s", "p50_ms": float(np.median(lat) * 1e3),
-                  "p99_ms": float(np.quantile(lat, 0.99) * 1e3), "reps": args.plain_reps,
-                  "max_dev_from_batched": plain_dev},
-        "batched_over_plain": value / plain_value,
+        "plain": plain,
+        "batched_over_plain": value / plain["value"] if plain else None,
         "path_tflops_alg": alg_flops * B * args.steps / dt / 1e12,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "k_gemm (complex FP64 MFMA)", "avg_launch_ms": avg_launch_ms,
-                     "launches": launches},
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-scaled)",
+                     "traffic_source": traffic_note,
+                     "alg_bytes_per_launch": gemm_bytes / max(launches, 1),
+                     "alg_flops_per_launch": gemm_flops / max(launches, 1),
+                     "kernel": GEMM_KERNEL + " (mode 0: Schur complements, selected-inversion products)",
+                     "avg_launch_ms": avg_launch_ms, "launches": launches},
         "cpu_baseline": cpu,
         "parity": parity,
         "status_ok": bool((status == 0).all()),

@@ -130,12 +130,24 @@ int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const do
  * 0, CL_ESINGULAR or CL_ENONFINITE. Returns 0 or an API error. */
 int cl_status(cl_batch batch, int32_t* per_config_host);
 /* Measurement support: with profiling on (eager path only), every launch of the
- * complex GEMM kernel is bracketed by HIP events on the batch stream. _read waits
- * for the stream, returns the summed kernel time (ms), the summed algorithmic flops
- * (8*M*N*K per product) and the number of timed launches since the last read, and
- * resets the counters. */
-int cl_batch_profile(cl_batch batch, int32_t enable);
-int cl_batch_profile_read(cl_batch batch, double* gemm_ms, double* gemm_flops, int64_t* launches);
+ * complex GEMM kernel in a selected mode is bracketed by HIP events on the batch
+ * stream. gemm_modes is a bit mask: bit 0 = mode 0 (C = alpha*A*B [+ C0]: Schur
+ * complements and the selected-inversion products), bit 1 = mode 1 (pivot-block
+ * inverse times pivot rows), bit 2 = mode 2 (Gauss-Jordan elimination update);
+ * 0 turns it off, 7 times every GEMM. _read waits for the stream, returns the
+ * summed kernel time (ms), the summed algorithmic flops (8*M*N*K per product), the
+ * summed algorithmic bytes (16 bytes per complex element: each operand read once,
+ * the result written once, plus the C0 or base read where the mode has one) and the
+ * number of timed launches since the last read, and resets the counters. */
+int cl_batch_profile(cl_batch batch, int32_t gemm_modes);
+int cl_batch_profile_read(cl_batch batch, double* gemm_ms, double* gemm_flops, double* gemm_bytes,
+                          int64_t* launches);
+/* The same launches one by one, in launch order, before _read resets them: fills up
+ * to cap entries of ms, flops, bytes (host arrays of doubles) and mode (int32) and
+ * sets *n to the number of timed launches (which may exceed cap). Waits for the
+ * stream. NULL arrays are allowed only with cap == 0. */
+int cl_batch_profile_launches(cl_batch batch, int64_t cap, double* ms, double* flops,
+                              double* bytes, int32_t* mode, int64_t* n);
 /* Non-blocking: 1 if all work enqueued by the batch's last call has finished, 0 if
  * it is still running, negative on error. */
 int cl_batch_query(cl_batch batch);

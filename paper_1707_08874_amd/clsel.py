@@ -49,7 +49,7 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_plan_destroy", "cl_batch_create", "cl_batch_set_active", "cl_batch_use_graph",
            "cl_factor", "cl_selinv", "cl_drift", "cl_selected", "cl_run", "cl_status",
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
-           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_query", "cl_observables"]
+           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables"]
 
 
 def lib():
@@ -82,7 +82,10 @@ def lib():
         "cl_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "cl_last_error": (ctypes.c_char_p, []),
         "cl_batch_profile": (ctypes.c_int, [vp, ctypes.c_int32]),
-        "cl_batch_profile_read": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "cl_batch_profile_read": (ctypes.c_int, [vp, dp, dp, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "cl_batch_profile_launches": (ctypes.c_int, [vp, ctypes.c_int64, dp, dp, dp,
+                                                      ctypes.POINTER(ctypes.c_int32),
+                                                      ctypes.POINTER(ctypes.c_int64)]),
         "cl_batch_query": (ctypes.c_int, [vp]),
         "cl_observables": (ctypes.c_int, [vp, vp]),
     }
@@ -230,14 +233,30 @@ class Batch:
                             _dev_ptr(drift_out)))
         return selected_out, drift_out
 
-    def profile(self, enable: bool = True):
-        _check(lib().cl_batch_profile(self._h, 1 if enable else 0))
+    def profile(self, gemm_modes: int = 7):
+        """Time GEMM launches of the modes in the bit mask (0 = off, 7 = every mode)."""
+        _check(lib().cl_batch_profile(self._h, int(gemm_modes)))
 
     def profile_read(self):
-        """(summed GEMM kernel ms, summed algorithmic GEMM flops, launches) since the last read."""
-        ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        _check(lib().cl_batch_profile_read(self._h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(n)))
-        return ms.value, fl.value, n.value
+        """(summed GEMM kernel ms, algorithmic flops, algorithmic bytes, launches) of the
+        timed launches since the last read."""
+        ms, fl, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        _check(lib().cl_batch_profile_read(self._h, ctypes.byref(ms), ctypes.byref(fl),
+                                           ctypes.byref(by), ctypes.byref(n)))
+        return ms.value, fl.value, by.value, n.value
+
+    def profile_launches(self):
+        """Per timed launch since the last profile_read: dict of arrays ms, flops, bytes, mode."""
+        n = ctypes.c_int64()
+        _check(lib().cl_batch_profile_launches(self._h, 0, None, None, None, None, ctypes.byref(n)))
+        k = n.value
+        ms, fl, by = (np.zeros(k) for _ in range(3))
+        mode = np.zeros(k, dtype=np.int32)
+        dptr = ctypes.POINTER(ctypes.c_double)
+        _check(lib().cl_batch_profile_launches(
+            self._h, k, ms.ctypes.data_as(dptr), fl.ctypes.data_as(dptr), by.ctypes.data_as(dptr),
+            mode.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(n)))
+        return {"ms": ms, "flops": fl, "bytes": by, "mode": mode}
 
     def status(self) -> np.ndarray:
         out = np.zeros(self.active, dtype=np.int32)

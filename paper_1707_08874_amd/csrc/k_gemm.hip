@@ -2,12 +2,15 @@
 //
 // A complex product C = A*B is four real products: Re C = Ar*Br - Ai*Bi,
 // Im C = Ar*Bi + Ai*Br (no 3M trick, so rounding matches the plain 4-multiply form).
-// Each work-group computes a BM x BN complex tile (64 x 64 or 128 x 128) with 4 waves
-// (2 x 2), each wave a (BM/2) x (BN/2) tile made of TM x TN MFMA tiles of 16 x 16 with two FP64 accumulators
-// (real part fed by Ar*Br and (-Ai)*Bi, imaginary part by Ar*Bi and Ai*Br). K advances
-// 16 complex per stage through LDS, real and imaginary planes stored k-major so the
-// MFMA operand reads are contiguous; the next stage's global loads are issued into
-// registers before the current stage's MFMAs, so their latency overlaps the math.
+// Each work-group computes a BM x BN complex tile (64 x 64, or 128 x 64 / 128 x 128)
+// with 4 waves (2 x 2), each wave a (BM/2) x (BN/2) tile made of TM x TN MFMA tiles of
+// 16 x 16 with two FP64 accumulators (real part fed by Ar*Br and (-Ai)*Bi, imaginary
+// part by Ar*Bi and Ai*Br). K advances BK complex per stage through LDS, real and
+// imaginary planes stored k-major so the MFMA operand reads are contiguous. Each
+// stage's global loads go to registers one stage ahead; with two LDS buffers (the
+// 64 x 64 tile, BK = 8) the registers are stored into the idle buffer right after the
+// current stage's MFMAs, so there is one barrier per stage and the kernel fits four
+// waves per SIMD. The accumulation order over k is the same for every BK.
 //
 // MFMA 16x16x4 f64 lane layout (measured on gfx950): A operand lane l holds
 // A[l%16][l/16], B operand lane l holds B[l/16][l%16], accumulator element r of
@@ -26,7 +29,6 @@ namespace clsel {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int BK = 16;
 constexpr int kGemmThreads = 256;
 constexpr int kXcds = 8;
 
@@ -70,11 +72,13 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
   return x * q + min(x, r) + local;
 }
 
-template <int MODE, int TM, int TN>
+template <int MODE, int TM, int TN, int BK, int NBUF>
 __global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : 2)
 k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
-  constexpr int RA = BM / 16, RB = BN / 16;  // complex loads per thread per stage
+  constexpr int RA = BM * BK / kGemmThreads, RB = BN * BK / kGemmThreads;  // loads per thread per stage
+  static_assert(RA >= 1 && RB >= 1 && kGemmThreads % BK == 0 && BK % 4 == 0, "load mapping");
+  static_assert(NBUF == 1 || NBUF == 2, "one or two LDS buffers");
   const int b = blockIdx.y;
   const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
   int lo = 0, hi = ndesc - 1;
@@ -87,15 +91,17 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   const int row0 = (int)(tile / d.tiles_n) * BM;
   const int col0 = (int)(tile % d.tiles_n) * BN;
 
-  __shared__ double As[2][BK][BM + 1];
-  __shared__ double Bs[2][BK][BN + 1];
+  __shared__ double As[NBUF][2][BK][BM + 1];
+  __shared__ double Bs[NBUF][2][BK][BN + 1];
   static_assert(BN <= kGemmThreads && kGemmThreads % BN == 0, "B load mapping");
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int l16 = lane & 15, l4 = lane >> 4;
-  const int a_kk = tid & 15;          // A loads: rows (tid>>4) + 16r, k = tid & 15
+  const int a_kk = tid % BK;          // A loads: rows tid / BK + (256/BK) r, k = tid % BK
+  const int a_m0 = tid / BK;
+  constexpr int a_mstep = kGemmThreads / BK;
   const int b_n = tid % BN;           // B loads: col tid % BN, k rows tid / BN + (256/BN) r
   const int b_kk0 = tid / BN;
   constexpr int b_kstep = kGemmThreads / BN;
@@ -107,7 +113,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   Operands<MODE, RA> o;
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
-    const int i = row0 + (tid >> 4) + 16 * r;
+    const int i = row0 + a_m0 + a_mstep * r;
     o.ai[r] = i;
     o.arow[r] = nullptr;
     if (i < d.M) {
@@ -143,10 +149,6 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     }
 
   double2 pa[RA], pb[RB];
-#pragma unroll
-  for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, a_kk);
-#pragma unroll
-  for (int r = 0; r < RB; ++r) pb[r] = ld_b(b_kk0 + b_kstep * r);
 
   // mode 2: the old front values that the update is subtracted from, loaded during the
   // last K stage so the loads overlap its MFMAs
@@ -168,35 +170,41 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       }
   };
 
-  auto store_stage = [&]() {
+  auto load_stage = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + b_kk0 + b_kstep * r);
+  };
+  auto store_stage = [&](int buf) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) {
-      const int m = (tid >> 4) + 16 * r;
-      As[0][a_kk][m] = pa[r].x;
-      As[1][a_kk][m] = pa[r].y;
+      const int m = a_m0 + a_mstep * r;
+      As[buf][0][a_kk][m] = pa[r].x;
+      As[buf][1][a_kk][m] = pa[r].y;
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       const int kk = b_kk0 + b_kstep * r;
-      Bs[0][kk][b_n] = pb[r].x;
-      Bs[1][kk][b_n] = pb[r].y;
+      Bs[buf][0][kk][b_n] = pb[r].x;
+      Bs[buf][1][kk][b_n] = pb[r].y;
     }
   };
-  auto mfma_stage = [&]() {
+  auto mfma_stage = [&](int buf) {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kk = 4 * k4 + l4;
       double ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
 #pragma unroll
       for (int i = 0; i < TM; ++i) {
-        ar[i] = As[0][kk][wm * (BM / 2) + i * 16 + l16];
-        ai[i] = As[1][kk][wm * (BM / 2) + i * 16 + l16];
+        ar[i] = As[buf][0][kk][wm * (BM / 2) + i * 16 + l16];
+        ai[i] = As[buf][1][kk][wm * (BM / 2) + i * 16 + l16];
         nai[i] = -ai[i];
       }
 #pragma unroll
       for (int j = 0; j < TN; ++j) {
-        br[j] = Bs[0][kk][wn * (BN / 2) + j * 16 + l16];
-        bi[j] = Bs[1][kk][wn * (BN / 2) + j * 16 + l16];
+        br[j] = Bs[buf][0][kk][wn * (BN / 2) + j * 16 + l16];
+        bi[j] = Bs[buf][1][kk][wn * (BN / 2) + j * 16 + l16];
       }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
@@ -215,23 +223,37 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     }
   };
 
-  // all stages but the last: store the prefetched stage, prefetch the next, MFMAs
-  const int klast = ((d.K - 1) / BK) * BK;
-  for (int k0 = 0; k0 < klast; k0 += BK) {
-    store_stage();
+  const int nst = (d.K + BK - 1) / BK;
+  load_stage(0);
+  if (NBUF == 1) {
+    // one buffer: store the prefetched stage, prefetch the next, MFMAs, two barriers
+    for (int st = 0; st + 1 < nst; ++st) {
+      store_stage(0);
+      __syncthreads();
+      load_stage((st + 1) * BK);
+      mfma_stage(0);
+      __syncthreads();
+    }
+    store_stage(0);
     __syncthreads();
-#pragma unroll
-    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + BK + a_kk);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + BK + b_kk0 + b_kstep * r);
-    mfma_stage();
+    // mode 2 fetches its subtrahend during the last stage so the loads overlap the MFMAs
+    if (MODE == 2) load_base();
+    mfma_stage(0);
+  } else {
+    // two buffers: stage st+1 goes into the idle buffer after stage st's MFMAs (that
+    // buffer was last read in stage st-1, before the previous barrier): one barrier
+    store_stage(0);
     __syncthreads();
+    if (nst > 1) load_stage(BK);
+    for (int st = 0; st + 1 < nst; ++st) {
+      mfma_stage(st & 1);
+      store_stage((st + 1) & 1);
+      if (st + 2 < nst) load_stage((st + 2) * BK);
+      __syncthreads();
+    }
+    if (MODE == 2) load_base();
+    mfma_stage((nst - 1) & 1);
   }
-  // last stage; mode 2 fetches its subtrahend here so the loads overlap the MFMAs
-  store_stage();
-  __syncthreads();
-  if (MODE == 2) load_base();
-  mfma_stage();
 
 #pragma unroll
   for (int i = 0; i < TM; ++i)
@@ -263,11 +285,11 @@ void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* 
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride) {
   GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride};
   const dim3 blk(kGemmThreads);
-  if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4>), grid, blk, 0, st, descs, ndesc, g);
-  else if (mode == 0 && tile == kTile128x64) hipLaunchKernelGGL((k_gemm<0, 4, 2>), grid, blk, 0, st, descs, ndesc, g);
-  else if (mode == 0) hipLaunchKernelGGL((k_gemm<0, 2, 2>), grid, blk, 0, st, descs, ndesc, g);
-  else if (mode == 1) hipLaunchKernelGGL((k_gemm<1, 2, 2>), grid, blk, 0, st, descs, ndesc, g);
-  else hipLaunchKernelGGL((k_gemm<2, 2, 2>), grid, blk, 0, st, descs, ndesc, g);
+  if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 0 && tile == kTile128x64) hipLaunchKernelGGL((k_gemm<0, 4, 2, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 0) hipLaunchKernelGGL((k_gemm<0, 2, 2, 8, 2>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 1) hipLaunchKernelGGL((k_gemm<1, 2, 2, 8, 2>), grid, blk, 0, st, descs, ndesc, g);
+  else hipLaunchKernelGGL((k_gemm<2, 2, 2, 8, 2>), grid, blk, 0, st, descs, ndesc, g);
 }
 
 }  // namespace clsel

@@ -49,6 +49,7 @@ struct Launch {
   int64_t gridx;
   int rpt;           // panel rows per thread; GEMM mode for GEMM launches
   double flops = 0;  // per configuration: 8*M*N*K summed over the GEMM problems
+  double bytes = 0;  // per configuration: operands read once + result written once
   int tile = 64;     // GEMM output tile edge (64 or 128)
 };
 
@@ -280,7 +281,12 @@ void build_layout(const clsel::Plan& P, Layout& L) {
     for (Launch& l : *ls) {
       if (l.kind != kGemm) continue;
       const clsel::GemmDesc* d = (const clsel::GemmDesc*)(L.blob.data() + l.desc_off);
-      for (int i = 0; i < l.count; ++i) l.flops += 8.0 * d[i].M * d[i].N * d[i].K;
+      for (int i = 0; i < l.count; ++i) {
+        const double M = d[i].M, N = d[i].N, K = d[i].K;
+        const bool reads_c = d[i].mode == 2 || d[i].has_c0;  // base / C0 read beside A and B
+        l.flops += 8.0 * M * N * K;
+        l.bytes += 16.0 * (M * K + K * N + M * N * (reads_c ? 2 : 1));
+      }
     }
 }
 
@@ -437,11 +443,13 @@ struct cl_batch_s {
   void* g_drift = nullptr;
   int g_active = 0;
   // optional per-launch timing of the GEMM kernels (HIP events on the batch stream)
-  bool prof = false;
+  int prof = 0;                      // bit k set: time GEMM launches of mode k
   std::vector<hipEvent_t> prof_ev;   // pairs, recorded around each GEMM launch
   std::vector<double> prof_flops;    // algorithmic flops of each timed launch
+  std::vector<double> prof_bytes;    // algorithmic bytes of each timed launch
+  std::vector<int32_t> prof_mode;    // GEMM mode of each timed launch
   size_t prof_used = 0;
-  double prof_ms = 0, prof_flop_total = 0;
+  double prof_ms = 0, prof_flop_total = 0, prof_byte_total = 0;
   int64_t prof_launches = 0;
 };
 
@@ -494,7 +502,8 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
         break;
       case kGemm: {
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (b->prof) {
+        const bool timed = (b->prof >> l.rpt) & 1;
+        if (timed) {
           if (b->prof_used + 2 > b->prof_ev.size()) {
             for (int k = 0; k < 64; ++k) {
               hipEvent_t e;
@@ -506,12 +515,14 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
           e1 = b->prof_ev[b->prof_used + 1];
           b->prof_used += 2;
           b->prof_flops.push_back(l.flops * B);
+          b->prof_bytes.push_back(l.bytes * B);
+          b->prof_mode.push_back(l.rpt);
           HIPCHK(hipEventRecord(e0, b->st));
         }
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws,
                            b->L.iws_elems);
-        if (b->prof) HIPCHK(hipEventRecord(e1, b->st));
+        if (timed) HIPCHK(hipEventRecord(e1, b->st));
         break;
       }
       case kZss:
@@ -872,31 +883,57 @@ int cl_run(cl_batch b, const void* links_dev, const double* m_host, const double
   return end(b);
 }
 
-int cl_batch_profile(cl_batch b, int32_t enable) {
+int cl_batch_profile(cl_batch b, int32_t gemm_modes) {
   if (!b) return fail(CL_EINVAL, "null batch");
-  if (enable && b->use_graph) return fail(CL_EINVAL, "profiling needs the eager path");
-  b->prof = enable != 0;
+  if (gemm_modes < 0 || gemm_modes > 7) return fail(CL_EINVAL, "gemm_modes is a mask of bits 0..2");
+  if (gemm_modes && b->use_graph) return fail(CL_EINVAL, "profiling needs the eager path");
+  b->prof = gemm_modes;
   return 0;
 }
 
-int cl_batch_profile_read(cl_batch b, double* gemm_ms, double* gemm_flops, int64_t* launches) {
-  if (!b || !gemm_ms || !gemm_flops || !launches) return fail(CL_EINVAL, "null argument");
+int cl_batch_profile_read(cl_batch b, double* gemm_ms, double* gemm_flops, double* gemm_bytes,
+                          int64_t* launches) {
+  if (!b || !gemm_ms || !gemm_flops || !gemm_bytes || !launches)
+    return fail(CL_EINVAL, "null argument");
   HIPCHK(hipStreamSynchronize(b->st));
   for (size_t i = 0; i + 1 < b->prof_used; i += 2) {
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, b->prof_ev[i], b->prof_ev[i + 1]));
     b->prof_ms += ms;
     b->prof_flop_total += b->prof_flops[i / 2];
+    b->prof_byte_total += b->prof_bytes[i / 2];
     ++b->prof_launches;
   }
   b->prof_used = 0;
   b->prof_flops.clear();
+  b->prof_bytes.clear();
+  b->prof_mode.clear();
   *gemm_ms = b->prof_ms;
   *gemm_flops = b->prof_flop_total;
+  *gemm_bytes = b->prof_byte_total;
   *launches = b->prof_launches;
   b->prof_ms = 0;
   b->prof_flop_total = 0;
+  b->prof_byte_total = 0;
   b->prof_launches = 0;
+  return 0;
+}
+
+int cl_batch_profile_launches(cl_batch b, int64_t cap, double* ms, double* flops, double* bytes,
+                              int32_t* mode, int64_t* n) {
+  if (!b || !n || cap < 0 || (cap > 0 && (!ms || !flops || !bytes || !mode)))
+    return fail(CL_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(b->st));
+  const int64_t timed = (int64_t)(b->prof_used / 2);
+  for (int64_t i = 0; i < timed && i < cap; ++i) {
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, b->prof_ev[2 * i], b->prof_ev[2 * i + 1]));
+    ms[i] = t;
+    flops[i] = b->prof_flops[i];
+    bytes[i] = b->prof_bytes[i];
+    mode[i] = b->prof_mode[i];
+  }
+  *n = timed;
   return 0;
 }
 
