@@ -1,7 +1,9 @@
-"""Full-size parity on the 12^3x6 lattice (N = 31104), where the dense oracle is too
-large: closed forms for the free field and a pure gauge (every block), and the
-diagonal identity and Gauss law on a generic SL(3,C) configuration (every block and
-every drift component)."""
+"""Full-size parity on the 12^3x6 (N = 31104) and 16^3x8 (N = 98304) lattices, where the
+dense oracle is too large: closed forms for the free field and a pure gauge (every
+block), and the diagonal identity and Gauss law on a generic SL(3,C) configuration
+(every block and every drift component). mu = 1/N_t as in the large-lattice workload."""
+import time
+
 import numpy as np
 import pytest
 
@@ -13,44 +15,58 @@ from properties import diag_identity_violation, gauss_law_violation
 
 pytestmark = pytest.mark.gpu
 
-DIMS = (12, 12, 12, 6)
-M, MU = 0.05, 1.0 / 6.0
+LATTICES = [(12, 12, 12, 6), (16, 16, 16, 8)]
+M = 0.05
 
 
-@pytest.fixture(scope="module")
-def results():
+@pytest.fixture(scope="module", params=LATTICES, ids=lambda d: "x".join(map(str, d)))
+def results(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    print(f"\n[gpu] {DIMS}: free, pure gauge, generic (B = 3)", flush=True)
-    U0 = unit_links(DIMS)
-    Ug, g = pure_gauge_links(DIMS, 11, scale=0.2)  # kappa_1 bound 2.2e4 (scale 0.5: 4e7)
-    Ur = gen_links(DIMS, 0, 0.1)
-    plan = clsel.Plan(DIMS)
-    batch = clsel.Batch(plan, 3)
-    lt = torch.from_numpy(np.stack([U0, Ug, Ur])).to("cuda")
-    sel, drift = batch.run(lt, M, MU)
-    st = batch.status()
-    out = dict(sel=sel.cpu().numpy(), drift=drift.cpu().numpy(), status=st, g=g, links=[U0, Ug, Ur])
-    batch.close()
-    del sel, drift, lt
-    torch.cuda.empty_cache()
-    return out
+    dims = request.param
+    mu = 1.0 / dims[3]
+    U0 = unit_links(dims)
+    Ug, g = pure_gauge_links(dims, 11, scale=0.2)  # kappa_1 bound 2.2e4 at 12^3x6 (scale 0.5: 4e7)
+    Ur = gen_links(dims, 0, 0.1)
+    plan = clsel.Plan(dims)
+    # 12^3x6 runs the three configurations as one batch; 16^3x8 needs 221 GB of fronts
+    # per configuration, so one at a time
+    per = 3 if plan.bytes(3) < 100e9 else 1
+    sel, drift, status = [], [], []
+    for i in range(0, 3, per):
+        print(f"\n[gpu] {dims}: configurations {i}..{i + per - 1} of (free, pure gauge, generic)",
+              flush=True)
+        batch = clsel.Batch(plan, per)
+        lt = torch.from_numpy(np.stack([U0, Ug, Ur][i:i + per])).to("cuda")
+        t0 = time.perf_counter()
+        s, d = batch.run(lt, M, mu)
+        status += batch.status().tolist()
+        print(f"[gpu] {dims}: {per} configuration(s) in {time.perf_counter() - t0:.2f} s", flush=True)
+        sel.append(s.cpu().numpy())
+        drift.append(d.cpu().numpy())
+        batch.close()
+        del s, d, lt
+        torch.cuda.empty_cache()
+    return dict(dims=dims, mu=mu, sel=np.concatenate(sel), drift=np.concatenate(drift),
+                status=status, g=g, links=[U0, Ug, Ur])
 
 
 def test_status(results):
-    assert results["status"].tolist() == [0, 0, 0]
+    assert results["status"] == [0, 0, 0]
 
 
 def test_free_field_every_block(results):
-    ref = free_blocks(DIMS, M, MU)
-    assert block_errors(results["sel"][0], ref).max() < tolerance(kappa1_bound_free(DIMS, M, MU))
+    dims, mu = results["dims"], results["mu"]
+    ref = free_blocks(dims, M, mu)
+    assert block_errors(results["sel"][0], ref).max() < tolerance(kappa1_bound_free(dims, M, mu))
     assert np.abs(results["drift"][0]).max() < 1e-10
 
 
 def test_pure_gauge_every_block(results):
-    ref = pure_gauge_blocks(DIMS, M, MU, results["g"])
-    tol = tolerance(kappa1_bound_pure_gauge(DIMS, M, MU, results["g"]))
+    dims, mu = results["dims"], results["mu"]
+    ref = pure_gauge_blocks(dims, M, mu, results["g"])
+    tol = tolerance(kappa1_bound_pure_gauge(dims, M, mu, results["g"]))
     err = block_errors(results["sel"][1], ref).max()
     print(f"[gpu] pure gauge worst block {err:.2e}, tolerance {tol:.1e}", flush=True)
     assert err < tol
@@ -62,17 +78,18 @@ def test_generic_diag_identity_and_gauss_law(results):
     for this workload), propagated through each identity: the diagonal identity sums 9
     products D_{xy} Z_{yx}; the Gauss law sums 8 link terms, four of them conjugated by
     U^{-1} . U, which can amplify by cond_1(U)."""
+    dims, mu = results["dims"], results["mu"]
     U = results["links"][2]
     sel = results["sel"][2]
     budget = 1e-9
-    d_max = 0.5 * np.exp(MU) * np.abs(U).sum(axis=-1).max() + M
+    d_max = 0.5 * np.exp(mu) * np.abs(U).sum(axis=-1).max() + M
     z_max = np.abs(sel).sum(axis=-1).max()
     tol_diag = 9 * d_max * z_max * budget
     cu = (np.abs(U).sum(axis=-2).max(axis=-1) * np.abs(np.linalg.inv(U)).sum(axis=-2).max(axis=-1)).max()
     tol_gauss = 8 * (1 + cu) * budget
-    vd = diag_identity_violation(sel, U, DIMS, M, MU)
-    vg = gauss_law_violation(results["drift"][2], U, DIMS)
-    print(f"[gpu] 12^3x6 generic: diag identity {vd:.2e} (tol {tol_diag:.1e}), "
+    vd = diag_identity_violation(sel, U, dims, M, mu)
+    vg = gauss_law_violation(results["drift"][2], U, dims)
+    print(f"[gpu] {dims} generic: diag identity {vd:.2e} (tol {tol_diag:.1e}), "
           f"Gauss law {vg:.2e} (tol {tol_gauss:.1e})", flush=True)
     assert vd < tol_diag
     assert vg < tol_gauss
