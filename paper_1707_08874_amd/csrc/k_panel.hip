@@ -6,6 +6,8 @@
 //            row on ties), running an in-place Gauss-Jordan elimination of the
 //            candidate rows over the panel columns in register groups of 16
 //            columns, with the remaining groups updated lazily in a workspace copy;
+//            per column: a DPP arg-max in each wave, the wave winners' rows through
+//            LDS, one barrier, a DPP combine of the eight wave results;
 //   phase 2: inverts Pi, the nbk x nbk block of the chosen rows in pivot order, by
 //            Gauss-Jordan elimination without further pivoting in LDS;
 //   and records the row permutation of the step and the equation held by each
@@ -18,8 +20,64 @@
 namespace clsel {
 
 constexpr int kPanelThreads = 512;
+constexpr int kWaves = kPanelThreads / 64;
 constexpr int kGroup = 16;
 constexpr int kPiLd = kMaxNB + 1;
+
+// Cross-lane helpers for the pivot search. DPP moves stay in the vector ALU, so a
+// wave-wide reduction costs a few instructions per step and no LDS round trip.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xF, false);
+}
+// readlane moves 32 bits: a double goes as its two halves
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+// Largest v over the wave and, among the lanes holding it, the lowest i; every lane
+// returns both. Two passes of one instruction per step (maximum, then minimum over
+// DPP: quad permutes, row rotations by 4 and 8, row broadcasts 15 and 31), so the
+// comparison never goes through scalar condition masks. v is never NaN here.
+__device__ __forceinline__ void wave_argmax(double& v, int& i) {
+  double m = v;
+  m = fmax(m, dpp_f64<0xB1, 0xF>(m));
+  m = fmax(m, dpp_f64<0x4E, 0xF>(m));
+  m = fmax(m, dpp_f64<0x124, 0xF>(m));
+  m = fmax(m, dpp_f64<0x128, 0xF>(m));
+  m = fmax(m, dpp_f64<0x142, 0xA>(m));
+  m = fmax(m, dpp_f64<0x143, 0xC>(m));
+  m = readlane_f64(m, 63);
+  int k = v == m ? i : 0x7fffffff;
+  k = min(k, dpp_i32<0xB1, 0xF>(k));
+  k = min(k, dpp_i32<0x4E, 0xF>(k));
+  k = min(k, dpp_i32<0x124, 0xF>(k));
+  k = min(k, dpp_i32<0x128, 0xF>(k));
+  k = min(k, dpp_i32<0x142, 0xA>(k));
+  k = min(k, dpp_i32<0x143, 0xC>(k));
+  v = m;
+  i = __builtin_amdgcn_readlane(k, 63);
+}
+// The same over the kWaves wave results, lane l holding result l % 8.
+__device__ __forceinline__ void combine_waves(double& v, int& i) {
+  static_assert(kWaves == 8, "three DPP steps combine eight lanes");
+  double m = v;
+  m = fmax(m, dpp_f64<0xB1, 0xF>(m));
+  m = fmax(m, dpp_f64<0x4E, 0xF>(m));
+  m = fmax(m, dpp_f64<0x124, 0xF>(m));
+  int k = v == m ? i : 0x7fffffff;
+  k = min(k, dpp_i32<0xB1, 0xF>(k));
+  k = min(k, dpp_i32<0x4E, 0xF>(k));
+  k = min(k, dpp_i32<0x124, 0xF>(k));
+  v = m;
+  i = k;
+}
 
 template <int RPT>
 __global__ void __launch_bounds__(kPanelThreads)
@@ -35,9 +93,9 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   int32_t* IW = iws + b * iws_stride;
   const int cand = d.p - d.k, nbk = d.nbk, ld = d.ld, k = d.k;
 
-  __shared__ double2 s_prow[2][kGroup];
-  __shared__ double s_rv[2][kPanelThreads / 64];
-  __shared__ int s_ri[2][kPanelThreads / 64];
+  __shared__ double2 s_cand[2][kWaves][kGroup];  // each wave's best row, per column parity
+  __shared__ double s_rv[2][kWaves];
+  __shared__ int s_ri[2][kWaves];
   __shared__ int s_piv[kMaxNB];
   __shared__ int s_flag;
   __shared__ double2 s_pcol[2][kMaxNB];
@@ -56,6 +114,7 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   double2 cur[RPT][kGroup];
 #pragma unroll
   for (int j = 0; j < RPT; ++j) used[j] = false;
+  const int lane = tid & 63, wave = tid >> 6;
 
   // ---- phase 1: pivot choice
   for (int g0 = 0; g0 < nbk; g0 += kGroup) {
@@ -69,71 +128,80 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
       for (int c = 0; c < kGroup; ++c)
         cur[j][c] = (live && c < gw) ? src[c] : make_double2(0.0, 0.0);
     }
-    for (int c = 0; c < gw; ++c) {
-      double best = -1.0;
-      int bi = 0x7fffffff;
+    // Each column step rotates the row registers by one slot: the column being
+    // eliminated is always slot 0, the updated later columns move down one slot and
+    // the multiplier goes to the last slot, so every register index is a constant.
+    // All 16 steps run (steps past the group width only rotate), which brings the frame
+    // back: slot t then holds the multiplier of the group's pivot t.
+    auto column_step = [&](int c) {
+      if (c < gw) {
+        double best = -1.0;
+        int bi = 0x7fffffff;
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int r = tid + j * kPanelThreads;
-        double2 v = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int cc = 0; cc < kGroup; ++cc)
-          if (cc == c) v = cur[j][cc];
-        double a = cabs2(v);
-        if (!(a == a)) a = -0.5;  // NaN ranks below every number but is still a valid row
-        if (r < cand && !used[j] && a > best) { best = a; bi = r; }
-      }
-#pragma unroll
-      for (int off = 32; off > 0; off >>= 1) {
-        const double ov = __shfl_xor(best, off);
-        const int oi = __shfl_xor(bi, off);
-        if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-      }
-      const int par = c & 1;  // double-buffered partials and pivot row: 2 barriers per column
-      if ((tid & 63) == 0) { s_rv[par][tid >> 6] = best; s_ri[par][tid >> 6] = bi; }
-      __syncthreads();
-      double bb = s_rv[par][0];
-      int pr = s_ri[par][0];
-#pragma unroll
-      for (int w = 1; w < kPanelThreads / 64; ++w) {
-        const double v = s_rv[par][w];
-        const int iw = s_ri[par][w];
-        if (v > bb || (v == bb && iw < pr)) { bb = v; pr = iw; }
-      }
-      if (pr < 0 || pr >= cand) { pr = 0; bb = -1.0; }  // keeps every index in range
-      if (tid == 0) {
-        s_piv[g0 + c] = pr;
-        if (!(bb > 0.0) || !isfinite(bb)) s_flag = 1;
-      }
-#pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        if (tid + j * kPanelThreads == pr) {
-#pragma unroll
-          for (int cc = 0; cc < kGroup; ++cc) s_prow[par][cc] = cur[j][cc];
-          used[j] = true;
+        for (int j = 0; j < RPT; ++j) {
+          const int r = tid + j * kPanelThreads;
+          double a = cabs2(cur[j][0]);
+          if (!(a == a)) a = -0.5;  // NaN ranks below every number but is still a valid row
+          const bool take = r < cand && !used[j] && a > best;
+          best = take ? a : best;
+          bi = take ? r : bi;
         }
-      }
-      __syncthreads();
-      double2 dp = s_prow[par][c];
-      if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) dp = make_double2(1.0, 0.0);
-      const double2 invd = crecip(dp);
+        wave_argmax(best, bi);
+        // the lane holding its wave's best row publishes it: one barrier per column
+        const int par = c & 1;
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int r = tid + j * kPanelThreads;
-        if (r < cand && !used[j]) {
-          double2 f = make_double2(0.0, 0.0);
+        for (int j = 0; j < RPT; ++j)
+          if (tid + j * kPanelThreads == bi) {
 #pragma unroll
-          for (int cc = 0; cc < kGroup; ++cc)
-            if (cc == c) f = cur[j][cc];
-          const double2 fi = cmul(f, invd);
-#pragma unroll
-          for (int cc = 0; cc < kGroup; ++cc) {
-            if (cc == c) cur[j][cc] = make_double2(-fi.x, -fi.y);
-            else cur[j][cc] = cfms(cur[j][cc], fi, s_prow[par][cc]);
+            for (int cc = 0; cc < kGroup; ++cc) s_cand[par][wave][cc] = cur[j][cc];
           }
+        if (lane == 0) { s_rv[par][wave] = best; s_ri[par][wave] = bi; }
+        __syncthreads();
+        double bb = s_rv[par][lane & (kWaves - 1)];
+        int pr = s_ri[par][lane & (kWaves - 1)];
+        combine_waves(bb, pr);
+        int ww = (pr & (kPanelThreads - 1)) >> 6;  // the wave that owns row pr
+        if (pr < 0 || pr >= cand) { pr = 0; bb = -1.0; ww = 0; }  // keeps every index in range
+        const double2* pv = s_cand[par][ww];
+        if (tid == 0) {
+          s_piv[g0 + c] = pr;
+          if (!(bb > 0.0) || !isfinite(bb)) s_flag = 1;
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) used[j] = used[j] || (tid + j * kPanelThreads == pr);
+        double2 dp = pv[0];
+        if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) dp = make_double2(1.0, 0.0);
+        const double2 invd = crecip(dp);
+        // rows out of the elimination (pivots, rows past the candidates) take a zero
+        // multiplier and only rotate; their values are not read again
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const bool live = tid + j * kPanelThreads < cand && !used[j];
+          const double2 f = cmul(cur[j][0], invd);
+          const double2 fi = live ? f : make_double2(0.0, 0.0);
+#pragma unroll
+          for (int cc = 0; cc + 1 < kGroup; ++cc) cur[j][cc] = cfms(cur[j][cc + 1], fi, pv[cc + 1]);
+          cur[j][kGroup - 1] = make_double2(-fi.x, -fi.y);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const double2 t0 = cur[j][0];
+#pragma unroll
+          for (int cc = 0; cc + 1 < kGroup; ++cc) cur[j][cc] = cur[j][cc + 1];
+          cur[j][kGroup - 1] = t0;
         }
       }
+    };
+    // unrolled by 4 where the registers allow it (renaming makes the rotation free)
+    if constexpr (RPT <= 2) {
+#pragma unroll 4
+      for (int c = 0; c < kGroup; ++c) column_step(c);
+    } else {
+#pragma unroll 1
+      for (int c = 0; c < kGroup; ++c) column_step(c);
     }
+    __syncthreads();  // s_piv of this group
     // lazy update of the later column groups of the still-unused rows:
     // PW[r][cc] += sum_t W_r[t] * R[t][cc], R = group pivot rows at group start
     const int rest0 = g0 + gw, nrest = nbk - rest0;
