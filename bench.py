@@ -51,6 +51,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--scaling", action="store_true",
+                    help="selected inversion + drift time per configuration against lattice volume, "
+                         "beside the oracle's dense inverse on the host (up to --scaling-cpu-max N)")
+    ap.add_argument("--scaling-cpu-max", type=int, default=12288)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     args = ap.parse_args()
@@ -64,6 +68,9 @@ def main():
 
     from paper_1707_08874_amd import autotune, clsel
     from paper_1707_08874_amd.inputs import gen_batch
+
+    if args.scaling:
+        return scaling(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -221,6 +228,63 @@ def main():
         "status_ok": bool((status == 0).all()),
     }
     print(json.dumps(out))
+
+
+def scaling(args):
+    """Time per configuration of the whole path (plain, B = 1, graph replay) from 4^4 to
+    16^3x8, m = 0.05, mu = 1/N_t, eps = 0.1, with the oracle's dense LAPACK inverse of the
+    same D timed on the host where it fits (N <= --scaling-cpu-max)."""
+    import numpy as np
+    import torch
+
+    from paper_1707_08874_amd import autotune, clsel
+    from paper_1707_08874_amd.inputs import gen_links
+
+    rows = []
+    for dims in [(4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 4), (8, 8, 8, 8), (12, 12, 12, 6), (16, 16, 16, 8)]:
+        m, mu = 0.05, 1.0 / dims[3]
+        links = gen_links(dims, 0, 0.1)
+        plan = clsel.Plan(dims, **autotune.options(dims, 1))
+        info = plan.info()
+        V = info["volume"]
+        b = clsel.Batch(plan, 1)
+        big = V > 20000
+        b.use_graph(not big)  # the largest lattices: eager (one replay costs seconds anyway)
+        lt = torch.from_numpy(links[None].copy()).to("cuda")
+        sel = torch.empty((1, V, 9, 3, 3), dtype=torch.complex128, device="cuda")
+        drift = torch.empty((1, V, 4, 8), dtype=torch.complex128, device="cuda")
+        for _ in range(2):
+            b.run(lt, m, mu, sel, drift)
+        b.sync()
+        reps = 3 if big else 10
+        ts = []
+        for _ in range(reps):
+            t = time.perf_counter()
+            b.run(lt, m, mu, sel, drift)
+            b.sync()
+            ts.append(time.perf_counter() - t)
+        ok = bool((b.status() == 0).all())
+        b.close()
+        del lt, sel, drift
+        torch.cuda.empty_cache()
+        gpu_s = float(np.median(ts))
+        alg = info["flops_factor_alg"] + info["flops_selinv_alg"]
+        row = {"lattice": "x".join(map(str, dims)), "N": 3 * V, "gpu_ms": gpu_s * 1e3,
+               "alg_flops": alg, "gpu_tflops_alg": alg / gpu_s / 1e12,
+               "bytes_per_config": plan.bytes(1), "status_ok": ok,
+               "dense_inverse_flops": info["flops_dense_inverse"]}
+        if 3 * V <= args.scaling_cpu_max:
+            import oracle
+            t = time.perf_counter()
+            D = oracle.dirac_dense(links, dims, m, mu)
+            Z = oracle.inverse_dense(D)
+            row["cpu_dense_inverse_s"] = time.perf_counter() - t
+            row["gpu_speedup_vs_cpu_dense"] = row["cpu_dense_inverse_s"] / gpu_s
+            del D, Z
+        rows.append(row)
+        print(f"[scaling] {row}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "selected inversion + drift time per configuration vs volume "
+                                "(plain path, B = 1)", "cpu_cores": _blas_threads(), "rows": rows}))
 
 
 if __name__ == "__main__":
