@@ -15,7 +15,9 @@ What it computes, by plain definition (Sec. 3 of the paper):
 * the nine 3x3 blocks of Z on the nonzero pattern of D for every site,
 * the drift K_{a,x,nu} = tr[D^{-1} d_{a,x,nu} D] (Eq. 6) through the two-block
   reduction tr(P B) + tr(Q F) (Eq. 8), with the derivative blocks F, B formed
-  explicitly from the Gell-Mann matrices.
+  explicitly from the Gell-Mann matrices,
+* the complex Langevin step around it (Eqs. 3-5): the Wilson gauge action and its
+  drift, and the Euler update with an optional adaptive step (oracle/langevin.py).
 
 Pins: see tests/test_oracle_pins.py. Every function here is pinned by at least
 one test that does not reuse the function's own formula.
@@ -26,10 +28,13 @@ from .selinv import (gell_mann, inverse_dense, selected_blocks, drift_from_block
                      selected_and_drift, SLOT_NAMES)
 from .observables import chiral_condensate, number_density
 from .columns import inverse_columns, sampled_selected_check
+from .langevin import (plaquettes, wilson_action, staples, gauge_drift, drift_norm_max,
+                       step_size, langevin_step)
 
 __all__ = [
     "coords", "eta_phases", "hop_tables", "dirac_dense", "dirac_sparse",
     "link_derivative_blocks", "gell_mann", "inverse_dense", "selected_blocks",
     "drift_from_blocks", "selected_and_drift", "SLOT_NAMES", "chiral_condensate",
-    "number_density", "inverse_columns", "sampled_selected_check",
+    "number_density", "inverse_columns", "sampled_selected_check", "plaquettes",
+    "wilson_action", "staples", "gauge_drift", "drift_norm_max", "step_size", "langevin_step",
 ]

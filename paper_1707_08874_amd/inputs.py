@@ -133,3 +133,11 @@ def pure_gauge_links(dims, seed: int, scale: float = 0.5):
         nb = cc[0] + L[0] * (cc[1] + L[1] * (cc[2] + L[2] * cc[3]))
         links[:, nu] = g @ ginv[nb]
     return links, g
+
+
+def gen_noise(dims, seed: int) -> np.ndarray:
+    """Real Gaussian Langevin noise eta_{a,x,nu}, shape [V][4][8], with
+    <eta_a eta_b> = 2 delta_ab (the Euler discretisation of complex Langevin with
+    drift K = -dS/dz and generators normalised as tr(lambda_a lambda_b) = 2 delta_ab)."""
+    rng = np.random.default_rng(1_000_003 + int(seed))
+    return rng.normal(0.0, np.sqrt(2.0), (volume(dims), 4, 8))
