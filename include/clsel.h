@@ -122,6 +122,35 @@ int cl_selected(cl_batch batch, void* out_dev);
  *                (1/V) tr(D^{-1} dD/dmu)  (quark number density, d/dmu log det D / V) }.
  * Deterministic reduction. Enqueues only; needs cl_selinv first. */
 int cl_observables(cl_batch batch, void* out_dev);
+/* Gauge drift K^g = -dS_g/dz for every link (Sec. 2, Eq. 5: the drift is K^g + K^f).
+ * The paper names the Wilson gauge action without writing it; here it is the plaquette
+ * action continued to SL(3,C) links, beta sum_P [1 - (tr P + tr P^{-1}) / 6], periodic in
+ * every direction, differentiated with the same left Lie derivative as the fermion drift.
+ * beta_host [B] (host, finite); out_dev (device) receives [B][V][4][8] complex128, K_a for
+ * a = 1..8. Uses the links of the last cl_factor / cl_run. Enqueues only; CL_EORDER
+ * before the first factorisation. */
+int cl_gauge_drift(cl_batch batch, const double* beta_host, void* out_dev);
+/* One Euler step of the complex Langevin evolution (Sec. 2, Eqs. 3-4) for every link:
+ * U <- exp[i sum_a lambda_a (eps K_a + sqrt(eps) eta_a)] U, where U are the links of the
+ * last cl_factor / cl_run and K = K^f + K^g.
+ *   links_out_dev [B][V][4][3][3] complex128 (device): the new links; it may be the
+ *                 buffer the links were read from.
+ *   kf_dev        [B][V][4][8] complex128 (device): the fermion drift (cl_drift).
+ *   kg_dev        same layout (cl_gauge_drift), or NULL for the fermion drift alone.
+ *   eta_dev       [B][V][4][8] double (device): real Gaussian noise drawn by the caller
+ *                 (<eta_a eta_b> = 2 delta_ab in the standard Euler scheme).
+ *   eps_bar_host  [B] finite steps >= 0. kref_host [B] or NULL: where kref > 0 the step
+ *                 is adaptive, eps = eps_bar * kref / max over links of
+ *                 sqrt(sum_a |K_a|^2) (Sec. 4.1 uses an adaptive step without giving
+ *                 the rule; this is the rule of Aarts, James, Seiler and Stamatescu,
+ *                 2010), else eps = eps_bar.
+ *   eps_out_dev   [B] double (device) or NULL: the step used.
+ * The exponential is a scaled Taylor polynomial with squaring (relative error ~1e-15).
+ * Enqueues only; CL_EORDER before the first factorisation, CL_EINVAL for a negative or
+ * non-finite eps_bar or a non-finite kref. */
+int cl_langevin_update(cl_batch batch, void* links_out_dev, const void* kf_dev, const void* kg_dev,
+                       const void* eta_dev, const double* eps_bar_host, const double* kref_host,
+                       void* eps_out_dev);
 /* cl_factor + cl_selinv + cl_selected + cl_drift in one call; replayed from a
  * HIP graph when enabled. Either output pointer may be NULL. */
 int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host,

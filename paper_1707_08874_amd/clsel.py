@@ -49,7 +49,8 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_plan_destroy", "cl_batch_create", "cl_batch_set_active", "cl_batch_use_graph",
            "cl_factor", "cl_selinv", "cl_drift", "cl_selected", "cl_run", "cl_status",
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
-           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables"]
+           "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables",
+           "cl_gauge_drift", "cl_langevin_update"]
 
 
 def lib():
@@ -88,6 +89,8 @@ def lib():
                                                       ctypes.POINTER(ctypes.c_int64)]),
         "cl_batch_query": (ctypes.c_int, [vp]),
         "cl_observables": (ctypes.c_int, [vp, vp]),
+        "cl_gauge_drift": (ctypes.c_int, [vp, dp, vp]),
+        "cl_langevin_update": (ctypes.c_int, [vp, vp, vp, vp, vp, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -220,6 +223,38 @@ class Batch:
         out = self._alloc((self.active, 2)) if out is None else out
         _check(lib().cl_observables(self._h, _dev_ptr(out)))
         return out
+
+    def _per_config(self, v):
+        v = np.ascontiguousarray(np.broadcast_to(np.asarray(v, dtype=np.float64), (self.active,)))
+        return v, v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def gauge_drift(self, beta, out=None):
+        """[B][V][4][8] complex128: the Wilson gauge drift K^g of the links of the last
+        factorisation (beta per configuration or scalar)."""
+        out = self._alloc((self.active, self.V, 4, 8)) if out is None else out
+        _b, pb = self._per_config(beta)
+        _check(lib().cl_gauge_drift(self._h, pb, _dev_ptr(out)))
+        return out
+
+    def langevin_update(self, links_out, kf, eta, eps_bar, kref=None, kg=None, eps_out=None):
+        """One Euler step of the links of the last factorisation into links_out:
+        U <- exp[i sum_a lambda_a (eps K_a + sqrt(eps) eta_a)] U, K = kf (+ kg). eta is a
+        real float64 [B][V][4][8] tensor; kref (per configuration, > 0) makes the step
+        adaptive. Returns the [B] float64 tensor of steps used."""
+        import torch
+        self._check_links(links_out)
+        if eps_out is None:
+            eps_out = torch.empty((self.active,), dtype=torch.float64, device="cuda")
+        _e, pe = self._per_config(eps_bar)
+        if kref is not None:
+            _k, pk = self._per_config(kref)
+        else:
+            pk = None
+        _check(lib().cl_langevin_update(self._h, _dev_ptr(links_out), _dev_ptr(kf),
+                                        _dev_ptr(kg) if kg is not None else None,
+                                        _dev_ptr(eta, "float64"), pe, pk,
+                                        _dev_ptr(eps_out, "float64")))
+        return eps_out
 
     def run(self, links, m, mu, selected_out=None, drift_out=None, want_selected=True):
         self._check_links(links)

@@ -45,6 +45,35 @@ __device__ __forceinline__ double2 cdiv(double2 a, double2 d) {
   }
 }
 
+// 3x3 complex helpers (row-major, 9 entries)
+__device__ __forceinline__ void mat3_mul(const double2* a, const double2* b, double2* c) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double2 s = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s = cfma(s, a[i * 3 + k], b[k * 3 + j]);
+      c[i * 3 + j] = s;
+    }
+}
+
+// K_a = tr(lambda_a M) for the eight standard Gell-Mann matrices
+// (tr(lambda_a lambda_b) = 2 delta_ab).
+__device__ __forceinline__ void gell_mann_traces(const double2* M, double2* o) {
+  const double2 m01 = M[1], m10 = M[3], m02 = M[2], m20 = M[6], m12 = M[5], m21 = M[7];
+  const double2 m00 = M[0], m11 = M[4], m22 = M[8];
+  const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
+  o[0] = cadd(m01, m10);
+  o[1] = make_double2(-(m01.y - m10.y), m01.x - m10.x);  // i (M01 - M10)
+  o[2] = csub(m00, m11);
+  o[3] = cadd(m02, m20);
+  o[4] = make_double2(-(m02.y - m20.y), m02.x - m20.x);
+  o[5] = cadd(m12, m21);
+  o[6] = make_double2(-(m12.y - m21.y), m12.x - m21.x);
+  o[7] = cscale(make_double2(m00.x + m11.x - 2.0 * m22.x, m00.y + m11.y - 2.0 * m22.y), is3);
+}
+
 struct LatticeDims {
   int L[4];
 };

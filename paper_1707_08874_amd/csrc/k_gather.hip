@@ -86,19 +86,7 @@ k_drift(const double2* __restrict__ sel, const double2* __restrict__ links,
       const double2 t = cadd(cscale(s1, cm), cscale(s2, cp));
       Mm[i * 3 + j] = make_double2(-t.y, t.x);  // multiply by i
     }
-  const double2 m01 = Mm[1], m10 = Mm[3], m02 = Mm[2], m20 = Mm[6], m12 = Mm[5], m21 = Mm[7];
-  const double2 m00 = Mm[0], m11 = Mm[4], m22 = Mm[8];
-  const double is3 = 0.57735026918962576451;  // 1/sqrt(3)
-  double2* o = out + e * 8;
-  // tr(lambda_a M) for the standard Gell-Mann matrices
-  o[0] = cadd(m01, m10);
-  o[1] = make_double2(-(m01.y - m10.y), m01.x - m10.x);  // i (M01 - M10)
-  o[2] = csub(m00, m11);
-  o[3] = cadd(m02, m20);
-  o[4] = make_double2(-(m02.y - m20.y), m02.x - m20.x);
-  o[5] = cadd(m12, m21);
-  o[6] = make_double2(-(m12.y - m21.y), m12.x - m21.x);
-  o[7] = cscale(make_double2(m00.x + m11.x - 2.0 * m22.x, m00.y + m11.y - 2.0 * m22.y), is3);
+  gell_mann_traces(Mm, out + e * 8);
 }
 
 // Fermionic observables from the selected blocks (the paper notes they need only the

@@ -35,6 +35,15 @@ __global__ void k_drift(const double2* sel, const double2* links, const double2*
 __global__ void k_observables(const double2* sel, const double2* links, const double2* linv,
                               const double* muvals, LatticeDims dims, int64_t V, double2* out);
 
+__global__ void k_gauge_drift(const double2* links, const double2* linv, const double* betas,
+                              LatticeDims dims, int64_t V, double2* out);
+__global__ void k_drift_max(const double2* kf, const double2* kg, int64_t V,
+                            unsigned long long* kmax_bits);
+__global__ void k_langevin_update(const double2* links_in, double2* links_out, const double2* kf,
+                                  const double2* kg, const double* eta, const double* eps_bar,
+                                  const double* kref, const unsigned long long* kmax_bits,
+                                  int64_t V, double* eps_out);
+
 void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs,
                   const double2* fronts, int64_t cfg_stride, double2* ws, int64_t ws_stride,
                   int32_t* iws, int64_t iws_stride, int32_t* status);

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -427,6 +428,10 @@ struct cl_batch_s {
   double2* linv = nullptr;
   double2* sel = nullptr;
   double* params = nullptr;       // device: m[cap], mu[cap]
+  double* lparams = nullptr;      // device: beta[cap], eps_bar[cap], kref[cap] (Langevin step)
+  double* lparams_host = nullptr; // pinned staging of lparams
+  hipEvent_t ev_lparam = nullptr; // the last lparams upload has left the pinned buffer
+  unsigned long long* kmax = nullptr;  // device [cap]: max_link |K| as a bit pattern
   double* params_host = nullptr;  // pinned staging
   int32_t* status = nullptr;
   char* dblob = nullptr;
@@ -611,6 +616,9 @@ void free_batch(cl_batch b) {
   if (b->gexec) hipGraphExecDestroy(b->gexec);
   hipFree(b->fronts); hipFree(b->ws); hipFree(b->iws); hipFree(b->links); hipFree(b->linv);
   hipFree(b->sel); hipFree(b->params); hipFree(b->status); hipFree(b->dblob);
+  hipFree(b->lparams); hipFree(b->kmax);
+  if (b->lparams_host) hipHostFree(b->lparams_host);
+  if (b->ev_lparam) hipEventDestroy(b->ev_lparam);
   hipFree(b->d_front_sites); hipFree(b->d_inv); hipFree(b->d_rel); hipFree(b->d_sel_off);
   hipFree(b->d_sel_ld);
   if (b->params_host) hipHostFree(b->params_host);
@@ -765,6 +773,15 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
   TRY(dalloc(&b->linv, (size_t)(B * b->L.links_elems)));
   TRY(dalloc(&b->sel, (size_t)(B * b->L.sel_elems)));
   TRY(dalloc(&b->params, (size_t)(2 * B)));
+  TRY(dalloc(&b->lparams, (size_t)(3 * B)));
+  TRY(dalloc(&b->kmax, (size_t)B));
+  {
+    hipError_t e = hipHostMalloc((void**)&b->lparams_host, sizeof(double) * 3 * B, hipHostMallocDefault);
+    if (e != hipSuccess) { b->lparams_host = nullptr; free_batch(b); return fail(CL_ENOMEM, "pinned staging"); }
+    std::memset(b->lparams_host, 0, sizeof(double) * 3 * B);
+  }
+  HTRY(hipEventCreateWithFlags(&b->ev_lparam, hipEventDisableTiming));
+  HTRY(hipEventRecord(b->ev_lparam, b->st));
   TRY(dalloc(&b->status, (size_t)B));
   {
     hipError_t e = hipHostMalloc((void**)&b->params_host, sizeof(double) * 2 * B, hipHostMallocDefault);
@@ -843,6 +860,63 @@ int cl_observables(cl_batch b, void* out) {
   const clsel::Plan& P = b->plan->P;
   hipLaunchKernelGGL(clsel::k_observables, dim3(b->active), dim3(256), 0, b->st, b->sel, b->links,
                      b->linv, b->params + b->cap, ldims(P), P.V, (double2*)out);
+  HIPCHK(hipGetLastError());
+  return end(b);
+}
+
+int cl_gauge_drift(cl_batch b, const double* beta, void* out) {
+  if (!b || !beta || !out) return fail(CL_EINVAL, "null argument");
+  if (b->state < 1) return fail(CL_EORDER, "cl_gauge_drift before cl_factor");
+  for (int i = 0; i < b->active; ++i)
+    if (!std::isfinite(beta[i])) return fail(CL_EINVAL, "non-finite beta");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  HIPCHK(hipEventSynchronize(b->ev_lparam));
+  for (int i = 0; i < b->active; ++i) b->lparams_host[i] = beta[i];
+  HIPCHK(hipMemcpyAsync(b->lparams, b->lparams_host, sizeof(double) * 3 * b->cap,
+                        hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipEventRecord(b->ev_lparam, b->st));
+  const clsel::Plan& P = b->plan->P;
+  const dim3 grid((unsigned)cdiv64(P.V * 4, 256), (unsigned)b->active);
+  hipLaunchKernelGGL(clsel::k_gauge_drift, grid, dim3(256), 0, b->st, b->links, b->linv,
+                     b->lparams, ldims(P), P.V, (double2*)out);
+  HIPCHK(hipGetLastError());
+  return end(b);
+}
+
+int cl_langevin_update(cl_batch b, void* links_out, const void* kf, const void* kg,
+                       const void* eta, const double* eps_bar, const double* kref, void* eps_out) {
+  if (!b || !links_out || !kf || !eta || !eps_bar) return fail(CL_EINVAL, "null argument");
+  if (b->state < 1) return fail(CL_EORDER, "cl_langevin_update before cl_factor");
+  bool adaptive = false;
+  for (int i = 0; i < b->active; ++i) {
+    if (!(eps_bar[i] >= 0.0) || !std::isfinite(eps_bar[i])) return fail(CL_EINVAL, "eps_bar must be finite and >= 0");
+    if (kref && !std::isfinite(kref[i])) return fail(CL_EINVAL, "non-finite kref");
+    adaptive = adaptive || (kref && kref[i] > 0.0);
+  }
+  int rc;
+  if ((rc = begin(b))) return rc;
+  HIPCHK(hipEventSynchronize(b->ev_lparam));
+  for (int i = 0; i < b->active; ++i) {
+    b->lparams_host[b->cap + i] = eps_bar[i];
+    b->lparams_host[2 * b->cap + i] = kref ? kref[i] : 0.0;
+  }
+  HIPCHK(hipMemcpyAsync(b->lparams, b->lparams_host, sizeof(double) * 3 * b->cap,
+                        hipMemcpyHostToDevice, b->st));
+  HIPCHK(hipEventRecord(b->ev_lparam, b->st));
+  const clsel::Plan& P = b->plan->P;
+  const dim3 grid((unsigned)cdiv64(P.V * 4, 256), (unsigned)b->active);
+  if (adaptive) {
+    hipLaunchKernelGGL(k_fill_i32, dim3((2 * b->active + 255) / 256), dim3(256), 0, b->st,
+                       (int32_t*)b->kmax, 2 * b->active, 0);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(clsel::k_drift_max, grid, dim3(256), 0, b->st, (const double2*)kf,
+                       (const double2*)kg, P.V, b->kmax);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(clsel::k_langevin_update, grid, dim3(256), 0, b->st, b->links,
+                     (double2*)links_out, (const double2*)kf, (const double2*)kg, (const double*)eta,
+                     b->lparams + b->cap, b->lparams + 2 * b->cap, b->kmax, P.V, (double*)eps_out);
   HIPCHK(hipGetLastError());
   return end(b);
 }
