@@ -55,6 +55,9 @@ def main():
                     help="selected inversion + drift time per configuration against lattice volume, "
                          "beside the oracle's dense inverse on the host (up to --scaling-cpu-max N)")
     ap.add_argument("--scaling-cpu-max", type=int, default=12288)
+    ap.add_argument("--langevin", action="store_true",
+                    help="complex Langevin steps (exact fermion drift + gauge drift + update) on the "
+                         "batched workload")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     args = ap.parse_args()
@@ -71,6 +74,8 @@ def main():
 
     if args.scaling:
         return scaling(args)
+    if args.langevin:
+        return langevin(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -227,6 +232,66 @@ def main():
         "parity": parity,
         "status_ok": bool((status == 0).all()),
     }
+    print(json.dumps(out))
+
+
+def langevin(args):
+    """Complex Langevin evolution of the batched workload (64 x 8^3x4, m = 0.05, mu = 0.25,
+    beta = 5.0, eps_bar = 0.001 as in the paper's runs, adaptive step with K_ref = the first
+    step's largest drift): per step, the selected inversion and fermion drift (cl_run without
+    the selected blocks), the gauge drift and the update. Timed per part with the stream
+    synchronised between parts, and as whole steps."""
+    import numpy as np
+    import torch
+
+    from paper_1707_08874_amd import autotune, clsel
+    from paper_1707_08874_amd.inputs import gen_batch, gen_noise
+
+    dims, m, mu, beta, eps_bar, B = (8, 8, 8, 4), 0.05, 0.25, 5.0, 0.001, args.batch
+    links = torch.from_numpy(gen_batch(dims, range(B))).to("cuda")
+    plan = clsel.Plan(dims, **autotune.options(dims, B))
+    V = plan.info()["volume"]
+    b = clsel.Batch(plan, B)
+    kf = torch.empty((B, V, 4, 8), dtype=torch.complex128, device="cuda")
+    nxt = torch.empty_like(links)
+    noise = [torch.from_numpy(np.stack([gen_noise(dims, 1000 * s + i) for i in range(B)])).to("cuda")
+             for s in range(2)]
+    # K_ref: the largest drift of the first configuration set (a fixed reference)
+    b.run(links, m, mu, None, kf, want_selected=False)
+    kg = b.gauge_drift(beta)
+    kref = float((kf + kg).abs().pow(2).sum(-1).sqrt().amax().item())
+    parts = {"selinv_fermion_drift": 0.0, "gauge_drift": 0.0, "update": 0.0}
+    eps_used = []
+    for it in range(args.warmup + args.steps):
+        timed = it >= args.warmup
+        t0 = time.perf_counter()
+        b.run(links, m, mu, None, kf, want_selected=False)
+        b.sync()
+        t1 = time.perf_counter()
+        b.gauge_drift(beta, out=kg)
+        b.sync()
+        t2 = time.perf_counter()
+        e = b.langevin_update(nxt, kf, noise[it % 2], eps_bar, kref=kref, kg=kg)
+        b.sync()
+        t3 = time.perf_counter()
+        links, nxt = nxt, links
+        if timed:
+            parts["selinv_fermion_drift"] += t1 - t0
+            parts["gauge_drift"] += t2 - t1
+            parts["update"] += t3 - t2
+            eps_used.append(e.cpu().numpy())
+    st = b.status()
+    b.close()
+    total = sum(parts.values())
+    out = {"metric": "complex Langevin steps/s with the exact drift (configurations x steps per second)",
+           "value": B * args.steps / total, "unit": "config-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": total / args.steps * 1e3, "higher_is_better": True,
+           "dtype": "c128", "data": "synthetic",
+           "config": {"workload": f"{B} x 8^3x4, m=0.05, mu=0.25, beta={beta}, eps_bar={eps_bar}, "
+                                  "adaptive step, K_ref = first step's max |K|"},
+           "ms_per_step_parts": {k: v / args.steps * 1e3 for k, v in parts.items()},
+           "eps_used_range": [float(np.min(eps_used)), float(np.max(eps_used))],
+           "status_ok": bool((st == 0).all())}
     print(json.dumps(out))
 
 
