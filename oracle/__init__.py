@@ -17,7 +17,9 @@ What it computes, by plain definition (Sec. 3 of the paper):
   reduction tr(P B) + tr(Q F) (Eq. 8), with the derivative blocks F, B formed
   explicitly from the Gell-Mann matrices,
 * the complex Langevin step around it (Eqs. 3-5): the Wilson gauge action and its
-  drift, and the Euler update with an optional adaptive step (oracle/langevin.py).
+  drift, and the Euler update with an optional adaptive step (oracle/langevin.py),
+* the stochastic estimate of the drift that selected inversion replaces (Eq. 7,
+  oracle/stochastic.py).
 
 Pins: see tests/test_oracle_pins.py. Every function here is pinned by at least
 one test that does not reuse the function's own formula.
@@ -30,6 +32,7 @@ from .observables import chiral_condensate, number_density
 from .columns import inverse_columns, sampled_selected_check
 from .langevin import (plaquettes, wilson_action, staples, gauge_drift, drift_norm_max,
                        step_size, langevin_step)
+from .stochastic import solve_dense, stochastic_blocks, stochastic_drift
 
 __all__ = [
     "coords", "eta_phases", "hop_tables", "dirac_dense", "dirac_sparse",
@@ -37,4 +40,5 @@ __all__ = [
     "drift_from_blocks", "selected_and_drift", "SLOT_NAMES", "chiral_condensate",
     "number_density", "inverse_columns", "sampled_selected_check", "plaquettes",
     "wilson_action", "staples", "gauge_drift", "drift_norm_max", "step_size", "langevin_step",
+    "solve_dense", "stochastic_blocks", "stochastic_drift",
 ]

@@ -141,3 +141,12 @@ def gen_noise(dims, seed: int) -> np.ndarray:
     drift K = -dS/dz and generators normalised as tr(lambda_a lambda_b) = 2 delta_ab)."""
     rng = np.random.default_rng(1_000_003 + int(seed))
     return rng.normal(0.0, np.sqrt(2.0), (volume(dims), 4, 8))
+
+
+def gen_sources(dims, n: int, seed: int) -> np.ndarray:
+    """Complex Gaussian noise columns xi, shape [N][n] (N = 3V), with E[xi xi^dagger] = 1:
+    real and imaginary parts N(0, 1/2)."""
+    rng = np.random.default_rng(2_000_029 + int(seed))
+    N = 3 * volume(dims)
+    s = np.sqrt(0.5)
+    return rng.normal(0.0, s, (N, n)) + 1j * rng.normal(0.0, s, (N, n))
