@@ -151,6 +151,26 @@ int cl_gauge_drift(cl_batch batch, const double* beta_host, void* out_dev);
 int cl_langevin_update(cl_batch batch, void* links_out_dev, const void* kf_dev, const void* kg_dev,
                        const void* eta_dev, const double* eps_bar_host, const double* kref_host,
                        void* eps_out_dev);
+/* Solves D X = R for ns right-hand sides through the factors of the last cl_factor /
+ * cl_run (forward sweep with -L^, backward sweep with A_JJ^{-1} and U^, front by front;
+ * valid before and after cl_selinv, which leaves the factors in place). rhs_dev and
+ * x_dev (device) are [B][N][ns] complex128 with row index 3*site + colour and the
+ * right-hand sides contiguous. 1 <= ns <= 4096. The first call for a given ns builds
+ * and checks its launch tables and allocates a workspace of 2 * (sum of front rows) * ns
+ * complex128 per configuration; calls with the same ns reuse them. Enqueues only;
+ * CL_EORDER before the first factorisation. */
+int cl_solve(cl_batch batch, const void* rhs_dev, int32_t ns, void* x_dev);
+/* Stochastic estimate of the selected blocks (Sec. 3, Eq. 7: the estimator that
+ * selected inversion replaces): from noise columns xi and X = D^{-1} xi (cl_solve), both
+ * [B][N][ns] complex128 (device), out_dev [B][V][9][3][3] complex128 receives
+ * Z~_{x,y} = (1/ns) sum_s X_{x,s} xi_{y,s}^* in the slot order of cl_selected. With
+ * E[xi xi^dagger] = 1 its expectation is the selected blocks of D^{-1}. Enqueues only. */
+int cl_stochastic_blocks(cl_batch batch, const void* xi_dev, const void* x_dev, int32_t ns,
+                         void* out_dev);
+/* The drift contraction of cl_drift (Eq. 8) applied to caller-supplied blocks in the
+ * layout of cl_selected (for example the stochastic estimate above), with the links and
+ * mu of the last cl_factor / cl_run. out_dev [B][V][4][8] complex128. Enqueues only. */
+int cl_drift_from_blocks(cl_batch batch, const void* blocks_dev, void* out_dev);
 /* cl_factor + cl_selinv + cl_selected + cl_drift in one call; replayed from a
  * HIP graph when enabled. Either output pointer may be NULL. */
 int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host,

@@ -50,7 +50,8 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_factor", "cl_selinv", "cl_drift", "cl_selected", "cl_run", "cl_status",
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
            "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables",
-           "cl_gauge_drift", "cl_langevin_update"]
+           "cl_gauge_drift", "cl_langevin_update", "cl_solve", "cl_stochastic_blocks",
+           "cl_drift_from_blocks"]
 
 
 def lib():
@@ -91,6 +92,9 @@ def lib():
         "cl_observables": (ctypes.c_int, [vp, vp]),
         "cl_gauge_drift": (ctypes.c_int, [vp, dp, vp]),
         "cl_langevin_update": (ctypes.c_int, [vp, vp, vp, vp, vp, dp, dp, vp]),
+        "cl_solve": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
+        "cl_stochastic_blocks": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp]),
+        "cl_drift_from_blocks": (ctypes.c_int, [vp, vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -255,6 +259,27 @@ class Batch:
                                         _dev_ptr(eta, "float64"), pe, pk,
                                         _dev_ptr(eps_out, "float64")))
         return eps_out
+
+    def solve(self, rhs, out=None):
+        """X = D^{-1} rhs for rhs [B][N][n] complex128 (N = 3V) with the factors of the
+        last factorisation."""
+        if rhs.dim() != 3 or rhs.shape[0] < self.active or rhs.shape[1] != 3 * self.V:
+            raise ClselError(CL_EINVAL, f"rhs must be [B][{3 * self.V}][n]")
+        out = self._alloc((self.active, 3 * self.V, rhs.shape[2])) if out is None else out
+        _check(lib().cl_solve(self._h, _dev_ptr(rhs), int(rhs.shape[2]), _dev_ptr(out)))
+        return out
+
+    def stochastic_blocks(self, xi, x, out=None):
+        """Z~ = (1/n) X xi^dagger on the selected pattern, [B][V][9][3][3]."""
+        out = self._alloc((self.active, self.V, 9, 3, 3)) if out is None else out
+        _check(lib().cl_stochastic_blocks(self._h, _dev_ptr(xi), _dev_ptr(x), int(xi.shape[2]),
+                                          _dev_ptr(out)))
+        return out
+
+    def drift_from_blocks(self, blocks, out=None):
+        out = self._alloc((self.active, self.V, 4, 8)) if out is None else out
+        _check(lib().cl_drift_from_blocks(self._h, _dev_ptr(blocks), _dev_ptr(out)))
+        return out
 
     def run(self, links, m, mu, selected_out=None, drift_out=None, want_selected=True):
         self._check_links(links)

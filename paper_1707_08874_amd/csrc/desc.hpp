@@ -14,7 +14,7 @@
 namespace clsel {
 
 // Pool selectors for plain GEMM operands.
-enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2 };
+enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2, kPoolRhs = 3 };
 
 // Front assembly: one entry per (front) of a level.
 struct AsmDesc {
@@ -70,6 +70,31 @@ struct GatherDesc {
   int64_t rel_off;        // s entries
   int64_t blk_start;
   int p, s, ld, par_ld;
+};
+
+// Solves D X = R through the frontal factors (R, X: n columns). Per front f the
+// right-hand-side workspace holds two H x n row-major blocks: R_f (assembled
+// right-hand side; its update rows later hold -X_S) at roff and X_f at xoff.
+struct RhsAsmDesc {        // R_f = rhs on the pivot rows + the children's update rows
+  int64_t roff;
+  int64_t site_off;
+  int64_t blk_start;
+  int H, p, nchild;
+  int64_t inv_off[4];
+  int64_t child_roff[4];
+  int child_p[4];
+};
+struct RhsGatherDesc {     // X_f[S] (and -X_f[S] into R_f[S]) from the parent's X
+  int64_t roff, xoff, par_xoff;
+  int64_t rel_off;
+  int64_t blk_start;
+  int p, s;
+};
+struct SolScatterDesc {    // pivot rows of X_f to the solution vector
+  int64_t xoff;
+  int64_t site_off;
+  int64_t blk_start;
+  int p;
 };
 
 }  // namespace clsel

@@ -414,6 +414,169 @@ __global__ void k_fill_i32(int32_t* p, int n, int32_t v) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- multi-RHS solves
+enum SolveKind { kRhsAsm = 10, kRhsGather, kSolScatter };
+
+struct SolveLayout {
+  int ns = 0;               // right-hand sides
+  int64_t rhs_elems = 0;    // complex workspace per configuration: R and X blocks
+  std::vector<char> blob;
+  std::vector<Launch> fwd, bwd;
+  Launch scatter{};
+};
+
+// Launch tables of X = D^{-1} R (see k_solve.hip): per level, leaves first, the
+// right-hand-side assembly and R_S += -L^ R_J; then per level, root first, the gather of
+// X_S and X_J = [A_JJ^{-1} | U^] [R_J; -X_S]; then the pivot rows to the solution.
+void build_solve_layout(const clsel::Plan& P, int ns, SolveLayout& S) {
+  S = SolveLayout{};
+  S.ns = ns;
+  const size_t nf = P.fronts.size();
+  std::vector<int64_t> roff(nf), xoff(nf);
+  int64_t acc = 0;
+  for (size_t f = 0; f < nf; ++f) { roff[f] = acc; acc += (int64_t)P.fronts[f].H * ns; }
+  for (size_t f = 0; f < nf; ++f) xoff[f] = acc + roff[f];
+  S.rhs_elems = 2 * acc;
+  const int64_t pool = P.pool_elems;
+  for (size_t lev = 0; lev < P.levels.size(); ++lev) {
+    std::vector<clsel::RhsAsmDesc> ad;
+    std::vector<clsel::GemmDesc> gs;
+    int64_t blk = 0;
+    for (int f : P.levels[lev]) {
+      const clsel::Front& fr = P.fronts[f];
+      clsel::RhsAsmDesc d{};
+      d.roff = roff[f];
+      d.site_off = fr.site_off;
+      d.blk_start = blk;
+      blk += cdiv64((int64_t)fr.H * ns, 256);
+      d.H = fr.H; d.p = fr.p; d.nchild = fr.nchild;
+      for (int c = 0; c < fr.nchild; ++c) {
+        d.inv_off[c] = fr.inv_off[c];
+        d.child_roff[c] = roff[fr.child[c]];
+        d.child_p[c] = P.fronts[fr.child[c]].p;
+      }
+      ad.push_back(d);
+      if (fr.s == 0) continue;
+      clsel::GemmDesc g{};  // R[S] += (-L^) R[J]
+      g.mode = 0; g.M = fr.s; g.N = ns; g.K = fr.p;
+      g.a_pool = fr.fbuf; g.a_off = fr.off + (int64_t)fr.p * fr.ld; g.lda = fr.ld;
+      g.b_pool = clsel::kPoolRhs; g.b_off = roff[f]; g.ldb = ns;
+      g.c_pool = clsel::kPoolRhs; g.c_off = roff[f] + (int64_t)fr.p * ns; g.ldc = ns;
+      g.c0_pool = clsel::kPoolRhs; g.c0_off = g.c_off; g.ldc0 = ns;
+      g.alpha = 1.0; g.has_c0 = 1;
+      gs.push_back(g);
+    }
+    S.fwd.push_back({kRhsAsm, blob_push(S.blob, ad.data(), ad.size() * sizeof(ad[0])), (int)ad.size(), blk, 0});
+    if (!gs.empty()) S.fwd.push_back(gemm_launch(S.blob, gs, 0, clsel::kTile64));
+  }
+  (void)pool;
+  for (int lev = (int)P.levels.size() - 1; lev >= 0; --lev) {
+    std::vector<clsel::RhsGatherDesc> gd;
+    std::vector<clsel::GemmDesc> gs;
+    int64_t blk = 0;
+    for (int f : P.levels[lev]) {
+      const clsel::Front& fr = P.fronts[f];
+      if (fr.s > 0) {
+        clsel::RhsGatherDesc d{};
+        d.roff = roff[f]; d.xoff = xoff[f]; d.par_xoff = xoff[fr.parent];
+        d.rel_off = fr.rel_off; d.blk_start = blk;
+        blk += cdiv64((int64_t)fr.s * ns, 256);
+        d.p = fr.p; d.s = fr.s;
+        gd.push_back(d);
+      }
+      clsel::GemmDesc g{};  // X[J] = [A_JJ^{-1} | U^] [R_J; -X_S]
+      g.mode = 0; g.M = fr.p; g.N = ns; g.K = fr.H;
+      g.a_pool = fr.fbuf; g.a_off = fr.off; g.lda = fr.ld;
+      g.b_pool = clsel::kPoolRhs; g.b_off = roff[f]; g.ldb = ns;
+      g.c_pool = clsel::kPoolRhs; g.c_off = xoff[f]; g.ldc = ns;
+      g.alpha = 1.0; g.has_c0 = 0;
+      gs.push_back(g);
+    }
+    if (!gd.empty())
+      S.bwd.push_back({kRhsGather, blob_push(S.blob, gd.data(), gd.size() * sizeof(gd[0])), (int)gd.size(), blk, 0});
+    S.bwd.push_back(gemm_launch(S.blob, gs, 0, clsel::kTile64));
+  }
+  std::vector<clsel::SolScatterDesc> sd;
+  int64_t blk = 0;
+  for (size_t f = 0; f < nf; ++f) {
+    const clsel::Front& fr = P.fronts[f];
+    sd.push_back({xoff[f], fr.site_off, blk, fr.p});
+    blk += cdiv64((int64_t)fr.p * ns, 256);
+  }
+  S.scatter = {kSolScatter, blob_push(S.blob, sd.data(), sd.size() * sizeof(sd[0])), (int)sd.size(), blk, 0};
+}
+
+// Host bounds check of every index the solve kernels and GEMMs can form.
+bool validate_solve_layout(const clsel::Plan& P, const SolveLayout& S, std::string& why) {
+  const int ns = S.ns;
+  const int64_t half = S.rhs_elems / 2, pool = P.pool_elems;
+  auto bad = [&](const char* what) { why = what; return false; };
+  auto desc = [&](const Launch& l) { return S.blob.data() + l.desc_off; };
+  for (const std::vector<Launch>* ls : {&S.fwd, &S.bwd})
+    for (const Launch& l : *ls) {
+      if (l.kind == kRhsAsm) {
+        const clsel::RhsAsmDesc* d = (const clsel::RhsAsmDesc*)desc(l);
+        int64_t blk = 0;
+        for (int i = 0; i < l.count; ++i) {
+          if (d[i].blk_start != blk) return bad("rhs assembly block start");
+          blk += cdiv64((int64_t)d[i].H * ns, 256);
+          if (d[i].roff + (int64_t)d[i].H * ns > half) return bad("rhs assembly block");
+          if (d[i].site_off + d[i].p / 3 > (int64_t)P.front_sites.size()) return bad("rhs sites");
+          if ((int64_t)d[i].H * ns >= (int64_t(1) << 31)) return bad("rhs 32-bit index");
+          for (int c = 0; c < d[i].nchild; ++c) {
+            if (d[i].inv_off[c] + d[i].H > (int64_t)P.inv_maps.size()) return bad("rhs inverse map");
+            for (int r = 0; r < d[i].H; ++r) {
+              const int ii = P.inv_maps[d[i].inv_off[c] + r];
+              if (ii >= 0 && d[i].child_roff[c] + (int64_t)(d[i].child_p[c] + ii + 1) * ns > half)
+                return bad("rhs child row");
+            }
+          }
+        }
+        if (blk != l.gridx) return bad("rhs assembly grid");
+      } else if (l.kind == kRhsGather) {
+        const clsel::RhsGatherDesc* d = (const clsel::RhsGatherDesc*)desc(l);
+        int64_t blk = 0;
+        for (int i = 0; i < l.count; ++i) {
+          if (d[i].blk_start != blk) return bad("rhs gather block start");
+          blk += cdiv64((int64_t)d[i].s * ns, 256);
+          if (d[i].rel_off + d[i].s > (int64_t)P.rel_maps.size()) return bad("rhs relative map");
+          if (d[i].xoff + (int64_t)(d[i].p + d[i].s) * ns > 2 * half || d[i].roff + (int64_t)(d[i].p + d[i].s) * ns > half)
+            return bad("rhs gather target");
+          for (int r = 0; r < d[i].s; ++r)
+            if (d[i].par_xoff + (int64_t)(P.rel_maps[d[i].rel_off + r] + 1) * ns > 2 * half) return bad("rhs gather source");
+        }
+        if (blk != l.gridx) return bad("rhs gather grid");
+      } else if (l.kind == kGemm) {
+        const clsel::GemmDesc* d = (const clsel::GemmDesc*)desc(l);
+        int64_t t = 0;
+        for (int i = 0; i < l.count; ++i) {
+          const clsel::GemmDesc& g = d[i];
+          if (g.mode != 0 || g.tile_start != t) return bad("solve gemm table");
+          t += cdiv64(g.M, 64) * g.tiles_n;
+          auto lim = [&](int pid) { return pid == clsel::kPoolRhs ? 2 * half : pool; };
+          if (g.a_off + (int64_t)(g.M - 1) * g.lda + g.K > lim(g.a_pool)) return bad("solve gemm A");
+          if (g.b_off + (int64_t)(g.K - 1) * g.ldb + g.N > lim(g.b_pool)) return bad("solve gemm B");
+          if (g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N > lim(g.c_pool)) return bad("solve gemm C");
+          if (g.has_c0 && g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N > lim(g.c0_pool)) return bad("solve gemm C0");
+        }
+        if (t != l.gridx) return bad("solve gemm grid");
+      } else {
+        return bad("solve launch kind");
+      }
+    }
+  const clsel::SolScatterDesc* d = (const clsel::SolScatterDesc*)desc(S.scatter);
+  int64_t blk = 0;
+  for (int i = 0; i < S.scatter.count; ++i) {
+    if (d[i].blk_start != blk) return bad("scatter block start");
+    blk += cdiv64((int64_t)d[i].p * ns, 256);
+    if (d[i].xoff + (int64_t)d[i].p * ns > 2 * half) return bad("scatter source");
+    for (int r = 0; r < d[i].p / 3; ++r)
+      if (P.front_sites[d[i].site_off + r] < 0 || P.front_sites[d[i].site_off + r] >= P.V) return bad("scatter site");
+  }
+  if (blk != S.scatter.gridx) return bad("scatter grid");
+  return true;
+}
+
 struct cl_batch_s {
   cl_plan plan = nullptr;
   Layout L;
@@ -432,6 +595,10 @@ struct cl_batch_s {
   double* lparams_host = nullptr; // pinned staging of lparams
   hipEvent_t ev_lparam = nullptr; // the last lparams upload has left the pinned buffer
   unsigned long long* kmax = nullptr;  // device [cap]: max_link |K| as a bit pattern
+  // multi-RHS solves: layout for the last n, its descriptors and the workspace
+  SolveLayout solve;
+  char* solve_blob = nullptr;
+  double2* rhs = nullptr;
   double* params_host = nullptr;  // pinned staging
   int32_t* status = nullptr;
   char* dblob = nullptr;
@@ -526,7 +693,7 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
         }
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws,
-                           b->L.iws_elems);
+                           b->L.iws_elems, nullptr, 0);
         if (timed) HIPCHK(hipEventRecord(e1, b->st));
         break;
       }
@@ -617,6 +784,7 @@ void free_batch(cl_batch b) {
   hipFree(b->fronts); hipFree(b->ws); hipFree(b->iws); hipFree(b->links); hipFree(b->linv);
   hipFree(b->sel); hipFree(b->params); hipFree(b->status); hipFree(b->dblob);
   hipFree(b->lparams); hipFree(b->kmax);
+  hipFree(b->solve_blob); hipFree(b->rhs);
   if (b->lparams_host) hipHostFree(b->lparams_host);
   if (b->ev_lparam) hipEventDestroy(b->ev_lparam);
   hipFree(b->d_front_sites); hipFree(b->d_inv); hipFree(b->d_rel); hipFree(b->d_sel_off);
@@ -917,6 +1085,107 @@ int cl_langevin_update(cl_batch b, void* links_out, const void* kf, const void* 
   hipLaunchKernelGGL(clsel::k_langevin_update, grid, dim3(256), 0, b->st, b->links,
                      (double2*)links_out, (const double2*)kf, (const double2*)kg, (const double*)eta,
                      b->lparams + b->cap, b->lparams + 2 * b->cap, b->kmax, P.V, (double*)eps_out);
+  HIPCHK(hipGetLastError());
+  return end(b);
+}
+
+namespace {
+constexpr int kMaxRhs = 4096;
+
+int prepare_solve(cl_batch b, int ns) {
+  if (b->solve.ns == ns && b->rhs) return 0;
+  const clsel::Plan& P = b->plan->P;
+  SolveLayout S;
+  build_solve_layout(P, ns, S);
+  std::string why;
+  if (!validate_solve_layout(P, S, why)) return fail(CL_EINVAL, "solve table check failed: " + why);
+  HIPCHK(hipStreamSynchronize(b->st));  // the old workspace may still be in use
+  hipFree(b->solve_blob); b->solve_blob = nullptr;
+  hipFree(b->rhs); b->rhs = nullptr;
+  b->solve = SolveLayout{};
+  int rc;
+  if ((rc = dalloc(&b->solve_blob, S.blob.size()))) return rc;
+  HIPCHK(hipMemcpy(b->solve_blob, S.blob.data(), S.blob.size(), hipMemcpyHostToDevice));
+  if ((rc = dalloc(&b->rhs, (size_t)(S.rhs_elems * b->cap)))) return rc;
+  b->solve = std::move(S);
+  return 0;
+}
+
+int enqueue_solve(cl_batch b, const void* rhs_dev, void* x_dev) {
+  const clsel::Plan& P = b->plan->P;
+  const SolveLayout& S = b->solve;
+  const int B = b->active, ns = S.ns;
+  const int64_t stride = S.rhs_elems, vstride = P.N * (int64_t)ns;
+  auto run = [&](const Launch& l) -> int {
+    if (l.gridx <= 0) return 0;
+    const dim3 grid((unsigned)l.gridx, (unsigned)B);
+    const char* dp = b->solve_blob + l.desc_off;
+    switch (l.kind) {
+      case kRhsAsm:
+        hipLaunchKernelGGL(clsel::k_rhs_assemble, grid, dim3(256), 0, b->st, (const clsel::RhsAsmDesc*)dp,
+                           l.count, b->rhs, stride, (const double2*)rhs_dev, vstride, b->d_front_sites,
+                           b->d_inv, ns);
+        break;
+      case kRhsGather:
+        hipLaunchKernelGGL(clsel::k_rhs_gather, grid, dim3(256), 0, b->st, (const clsel::RhsGatherDesc*)dp,
+                           l.count, b->rhs, stride, b->d_rel, ns);
+        break;
+      case kSolScatter:
+        hipLaunchKernelGGL(clsel::k_sol_scatter, grid, dim3(256), 0, b->st, (const clsel::SolScatterDesc*)dp,
+                           l.count, b->rhs, stride, (double2*)x_dev, vstride, b->d_front_sites, ns);
+        break;
+      default:
+        clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
+                           b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
+                           b->rhs, stride);
+    }
+    HIPCHK(hipGetLastError());
+    return 0;
+  };
+  int rc;
+  for (const Launch& l : S.fwd) if ((rc = run(l))) return rc;
+  for (const Launch& l : S.bwd) if ((rc = run(l))) return rc;
+  return run(S.scatter);
+}
+}  // namespace
+
+int cl_solve(cl_batch b, const void* rhs_dev, int32_t ns, void* x_dev) {
+  if (!b || !rhs_dev || !x_dev) return fail(CL_EINVAL, "null argument");
+  if (ns < 1 || ns > kMaxRhs) return fail(CL_EINVAL, "right-hand sides must be 1 .. 4096");
+  if (b->state < 1) return fail(CL_EORDER, "cl_solve before cl_factor");
+  int rc;
+  HIPCHK(hipSetDevice(b->device));
+  if ((rc = prepare_solve(b, ns))) return rc;
+  if ((rc = begin(b))) return rc;
+  if ((rc = enqueue_solve(b, rhs_dev, x_dev))) return rc;
+  return end(b);
+}
+
+int cl_stochastic_blocks(cl_batch b, const void* xi_dev, const void* x_dev, int32_t ns, void* out) {
+  if (!b || !xi_dev || !x_dev || !out) return fail(CL_EINVAL, "null argument");
+  if (ns < 1 || ns > kMaxRhs) return fail(CL_EINVAL, "samples must be 1 .. 4096");
+  if (b->state < 1) return fail(CL_EORDER, "cl_stochastic_blocks before cl_factor");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  const clsel::Plan& P = b->plan->P;
+  const dim3 grid((unsigned)cdiv64(P.V * 81, 256), (unsigned)b->active);
+  hipLaunchKernelGGL(clsel::k_stochastic_blocks, grid, dim3(256), 0, b->st, (const double2*)x_dev,
+                     (const double2*)xi_dev, ldims(P), P.V, ns, (double2*)out);
+  HIPCHK(hipGetLastError());
+  return end(b);
+}
+
+int cl_drift_from_blocks(cl_batch b, const void* blocks_dev, void* out) {
+  if (!b || !blocks_dev || !out) return fail(CL_EINVAL, "null argument");
+  if (b->state < 1) return fail(CL_EORDER, "cl_drift_from_blocks before cl_factor");
+  int rc;
+  if ((rc = begin(b))) return rc;
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active;
+  const int64_t n = P.V * 4 * (int64_t)B;
+  hipLaunchKernelGGL(clsel::k_drift, dim3((unsigned)cdiv64(n, 256)), dim3(256), 0, b->st,
+                     (const double2*)blocks_dev, b->links, b->linv, b->params + b->cap, ldims(P), P.V, B,
+                     (double2*)out);
   HIPCHK(hipGetLastError());
   return end(b);
 }
