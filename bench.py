@@ -55,6 +55,9 @@ def main():
                     help="selected inversion + drift time per configuration against lattice volume, "
                          "beside the oracle's dense inverse on the host (up to --scaling-cpu-max N)")
     ap.add_argument("--scaling-cpu-max", type=int, default=12288)
+    ap.add_argument("--stochastic", action="store_true",
+                    help="the stochastic drift estimator (Eq. 7) with 1, 10, 100 sources against the "
+                         "exact drift on the batched workload")
     ap.add_argument("--langevin", action="store_true",
                     help="complex Langevin steps (exact fermion drift + gauge drift + update) on the "
                          "batched workload")
@@ -76,6 +79,8 @@ def main():
         return scaling(args)
     if args.langevin:
         return langevin(args)
+    if args.stochastic:
+        return stochastic(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -233,6 +238,55 @@ def main():
         "status_ok": bool((status == 0).all()),
     }
     print(json.dumps(out))
+
+
+def stochastic(args):
+    """Stochastic estimate of the drift (Eq. 7) from n noise sources, with the same GPU
+    factors, against the exact drift of the selected inversion, on the batched workload
+    (64 x 8^3x4, m = 0.05, mu = 0.25). Reports the time per configuration of each and the
+    relative error ||K~ - K|| / ||K|| over all links of all configurations."""
+    import numpy as np
+    import torch
+
+    from paper_1707_08874_amd import autotune, clsel
+    from paper_1707_08874_amd.inputs import gen_batch, gen_sources
+
+    dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
+    links = torch.from_numpy(gen_batch(dims, range(B))).to("cuda")
+    plan = clsel.Plan(dims, **autotune.options(dims, B))
+    b = clsel.Batch(plan, B)
+    _s, kf = b.run(links, m, mu, want_selected=False)  # warm
+    b.sync()
+    t = time.perf_counter()
+    _s, kf = b.run(links, m, mu, want_selected=False)
+    b.sync()
+    exact_s = time.perf_counter() - t
+    ref = kf.cpu().numpy()
+    rows = []
+    for ns in (1, 10, 100):
+        xi = torch.from_numpy(np.stack([gen_sources(dims, ns, 7919 * ns + i) for i in range(B)])).to("cuda")
+        x = b.solve(xi)  # builds the tables for this n
+        b.sync()
+        t = time.perf_counter()
+        x = b.solve(xi, out=x)
+        est = b.stochastic_blocks(xi, x)
+        kd = b.drift_from_blocks(est)
+        b.sync()
+        dt = time.perf_counter() - t
+        k = kd.cpu().numpy()
+        rel = float(np.linalg.norm(k - ref) / np.linalg.norm(ref))
+        per_link = np.linalg.norm(k - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+        rows.append({"sources": ns, "ms_per_config": dt / B * 1e3, "rel_error": rel,
+                     "median_link_rel_error": float(np.median(per_link)),
+                     "p99_link_rel_error": float(np.quantile(per_link, 0.99))})
+        print(f"[stochastic] {rows[-1]}", file=sys.stderr, flush=True)
+        del xi, x, est, kd
+    st = b.status()
+    b.close()
+    print(json.dumps({"metric": "stochastic drift estimate (Eq. 7) against the exact drift, same GPU factors",
+                      "config": {"workload": f"{B} x 8^3x4, m=0.05, mu=0.25, complex Gaussian sources"},
+                      "exact_ms_per_config": exact_s / B * 1e3, "rows": rows,
+                      "status_ok": bool((st == 0).all())}))
 
 
 def langevin(args):
