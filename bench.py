@@ -200,10 +200,14 @@ def main():
         from paper_1707_08874_amd.profsum import source_digest
         with open(rec_path) as f:
             rec = json.load(f)
+        alg_live = gemm_bytes / max(launches, 1)
+        alg_rec = rec.get("alg_bytes_per_launch")
         if rec.get("source_sha256") != source_digest():
             traffic_note = "kernel source changed since the counters were taken"
         elif rec.get("workload") != workload:
             traffic_note = "counters were taken on another workload"
+        elif alg_rec is None or abs(alg_rec - alg_live) > 1e-9 * alg_live:
+            traffic_note = "the launches differ from those the counters were taken on"
         else:
             traffic, traffic_note = rec["bytes_per_launch"], rec.get("command", "")
     out = {

@@ -137,6 +137,9 @@ def main(argv=None):
     t.add_argument("--workload", type=json.loads, default=None,
                    help="JSON object naming the workload the counters were taken on")
     t.add_argument("--command", default="", help="the profiled command, for the record")
+    t.add_argument("--bench-log", default=None,
+                   help="output of the profiled bench run: its JSON line supplies the algorithmic "
+                        "bytes per launch, which identify the launch set the counters belong to")
     t.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -145,6 +148,11 @@ def main(argv=None):
     rec = traffic_record(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes)
     rec["workload"] = a.workload
     rec["command"] = a.command
+    if a.bench_log:
+        line = [ln for ln in open(a.bench_log) if ln.lstrip().startswith("{")][-1]
+        roof = json.loads(line)["roofline"]
+        rec["alg_bytes_per_launch"] = roof["alg_bytes_per_launch"]
+        rec["traffic_over_alg"] = rec["bytes_per_launch"] / roof["alg_bytes_per_launch"]
     text = json.dumps(rec, indent=1, sort_keys=True)
     if a.out:
         with open(a.out, "w") as f:
