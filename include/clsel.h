@@ -80,7 +80,7 @@ typedef struct {
 } cl_plan_info_t;
 
 /* Symbolic analysis of one lattice shape (host only, no device work). Every
- * extent must be even and >= 4. The plan is immutable and may be shared by any
+ * extent must be even and between 4 and 254. The plan is immutable and may be shared by any
  * number of batches and threads. Sec. 3: sparse LU followed by selected
  * inversion; the ordering is geometric nested dissection. */
 int cl_symbolic(const int32_t dims[4], cl_plan* out);

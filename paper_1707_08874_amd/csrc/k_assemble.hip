@@ -43,32 +43,35 @@ __global__ void k_link_inverse(const double2* __restrict__ links, double2* __res
   o[6] = cdiv(c02, det); o[7] = cdiv(c12, det); o[8] = cdiv(c22, det);
 }
 
-// Entry D_{(x,a),(y,b)} of the staggered operator (site indices fit in 32 bits).
-__device__ double2 dirac_entry(int x, int a, int y, int b, const double2* __restrict__ U,
-                               const double2* __restrict__ Uinv, double m, double emu,
-                               double emu_inv, const LatticeDims& dims) {
+// Entry D_{(x,a),(y,b)} of the staggered operator. Sites carry their coordinates packed
+// one byte per direction, so deciding that two sites are not neighbours (the common
+// case) takes a few bit operations and no division.
+__device__ __forceinline__ double2 dirac_entry(int x, int a, int y, int b, uint32_t px, uint32_t py,
+                                               const double2* __restrict__ U,
+                                               const double2* __restrict__ Uinv, double m,
+                                               double mu, const LatticeDims& dims) {
   if (x == y) return make_double2(a == b ? m : 0.0, 0.0);
-  int cx[4], cy[4];
-  {
-    int rx = x, ry = y;
+  const uint32_t diff = px ^ py;
+  int nu = -1, ndiff = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      cx[k] = rx % dims.L[k]; rx /= dims.L[k];
-      cy[k] = ry % dims.L[k]; ry /= dims.L[k];
-    }
-  }
-  int ndiff = 0, nu = -1;
   for (int k = 0; k < 4; ++k)
-    if (cx[k] != cy[k]) { ++ndiff; nu = k; }
+    if ((diff >> (8 * k)) & 0xFFu) { ++ndiff; nu = k; }
   if (ndiff != 1) return make_double2(0.0, 0.0);
   const int L = dims.L[nu];
-  if (cy[nu] == (cx[nu] + 1) % L) {  // y = x + nu: +c+(x,nu) U_{x,nu}
-    const double cp = dcplus(cx, nu, dims, emu);
-    return cscale(U[((int64_t)x * 4 + nu) * 9 + a * 3 + b], cp);
+  const int xn = (int)((px >> (8 * nu)) & 0xFFu), yn = (int)((py >> (8 * nu)) & 0xFFu);
+  if (yn == (xn + 1 == L ? 0 : xn + 1)) {  // y = x + nu: +c+(x,nu) U_{x,nu}
+    int cx[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cx[k] = (int)((px >> (8 * k)) & 0xFFu);
+    const double emu = nu == 3 ? exp(mu) : 1.0;  // only the temporal hop carries e^{mu}
+    return cscale(U[((int64_t)x * 4 + nu) * 9 + a * 3 + b], dcplus(cx, nu, dims, emu));
   }
-  if (cx[nu] == (cy[nu] + 1) % L) {  // x = y + nu: -c-(y,nu) U_{y,nu}^{-1}
-    const double cm = dcminus(cy, nu, dims, emu_inv);
-    return cscale(Uinv[((int64_t)y * 4 + nu) * 9 + a * 3 + b], -cm);
+  if (xn == (yn + 1 == L ? 0 : yn + 1)) {  // x = y + nu: -c-(y,nu) U_{y,nu}^{-1}
+    int cy[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) cy[k] = (int)((py >> (8 * k)) & 0xFFu);
+    const double emu_inv = nu == 3 ? exp(-mu) : 1.0;
+    return cscale(Uinv[((int64_t)y * 4 + nu) * 9 + a * 3 + b], -dcminus(cy, nu, dims, emu_inv));
   }
   return make_double2(0.0, 0.0);
 }
@@ -79,7 +82,8 @@ __device__ double2 dirac_entry(int x, int a, int y, int b, const double2* __rest
 __global__ void __launch_bounds__(256)
 k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ fronts,
            int64_t cfg_stride, const int32_t* __restrict__ front_sites,
-           const int32_t* __restrict__ inv_maps, const double2* __restrict__ links,
+           const int32_t* __restrict__ inv_maps, const uint32_t* __restrict__ site_coords,
+           const double2* __restrict__ links,
            const double2* __restrict__ linv, int64_t link_cfg_stride,
            const double* __restrict__ mvals, const double* __restrict__ muvals, LatticeDims dims,
            int32_t* __restrict__ iws, int64_t iws_stride) {
@@ -107,9 +111,9 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
   if (I < d.p || J < d.p) {
     const int x = front_sites[d.site_off + I / 3];
     const int y = front_sites[d.site_off + J / 3];
-    const double mu = muvals[b];
-    v = cadd(v, dirac_entry(x, I % 3, y, J % 3, links + b * link_cfg_stride,
-                            linv + b * link_cfg_stride, mvals[b], exp(mu), exp(-mu), dims));
+    v = cadd(v, dirac_entry(x, I % 3, y, J % 3, site_coords[x], site_coords[y],
+                            links + b * link_cfg_stride, linv + b * link_cfg_stride, mvals[b],
+                            muvals[b], dims));
   }
   F[(I < d.p ? d.joff : d.off) + (int64_t)I * d.ld + J] = v;
   if (e < d.p) iws[b * iws_stride + d.rowid_off + e] = (int32_t)e;

@@ -20,9 +20,9 @@ __global__ void k_link_inverse(const double2* links, double2* linv, int64_t link
                                int nbatch, int32_t* status);
 __global__ void k_assemble(const AsmDesc* descs, int ndesc, double2* fronts, int64_t cfg_stride,
                            const int32_t* front_sites, const int32_t* inv_maps,
-                           const double2* links, const double2* linv, int64_t link_cfg_stride,
-                           const double* mvals, const double* muvals, LatticeDims dims,
-                           int32_t* iws, int64_t iws_stride);
+                           const uint32_t* site_coords, const double2* links, const double2* linv,
+                           int64_t link_cfg_stride, const double* mvals, const double* muvals,
+                           LatticeDims dims, int32_t* iws, int64_t iws_stride);
 __global__ void k_gather_zss(const GatherDesc* descs, int ndesc, double2* fronts,
                              int64_t cfg_stride, const int32_t* rel_maps);
 __global__ void k_gather_selected(const double2* fronts, int64_t cfg_stride,

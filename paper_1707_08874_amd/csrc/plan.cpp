@@ -110,8 +110,8 @@ void neighbours(int64_t x, const int L[4], int64_t out[8]) {
 
 int build_plan(const int32_t dims[4], const PlanOptions& opt, Plan& P, std::string& err) {
   for (int d = 0; d < 4; ++d) {
-    if (dims[d] < 4 || dims[d] % 2 != 0) {
-      err = "every lattice extent must be even and at least 4";
+    if (dims[d] < 4 || dims[d] > 254 || dims[d] % 2 != 0) {
+      err = "every lattice extent must be even and between 4 and 254";
       return -1;
     }
   }
@@ -123,6 +123,16 @@ int build_plan(const int32_t dims[4], const PlanOptions& opt, Plan& P, std::stri
   P.opt = opt;
   int L[4];
   for (int d = 0; d < 4; ++d) { L[d] = dims[d]; P.dims[d] = dims[d]; }
+  {
+    const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
+    P.site_coords.resize(V);
+    for (int64_t x = 0; x < V; ++x) {
+      int c[4];
+      site_coords(x, L, c);
+      P.site_coords[x] = (int32_t)((uint32_t)c[0] | ((uint32_t)c[1] << 8) | ((uint32_t)c[2] << 16) |
+                                   ((uint32_t)c[3] << 24));
+    }
+  }
   P.V = (int64_t)L[0] * L[1] * L[2] * L[3];
   P.N = 3 * P.V;
 

@@ -53,6 +53,7 @@ struct Plan {
   std::vector<Front> fronts;                 // postorder: children before parents
   std::vector<std::vector<int>> levels;      // fronts per level, leaves first
   std::vector<int32_t> front_sites;          // pivot sites then update sites, per front
+  std::vector<int32_t> site_coords;          // [V] coordinates packed one byte each (x0 lowest)
   std::vector<int32_t> inv_maps;             // per (front, child slot): H_front entries
   std::vector<int32_t> rel_maps;             // per front: s entries
   std::vector<int32_t> site_front;           // front owning each site

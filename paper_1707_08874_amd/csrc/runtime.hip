@@ -603,6 +603,7 @@ struct cl_batch_s {
   int32_t* status = nullptr;
   char* dblob = nullptr;
   int32_t* d_front_sites = nullptr;
+  int32_t* d_site_coords = nullptr;
   int32_t* d_inv = nullptr;
   int32_t* d_rel = nullptr;
   int64_t* d_sel_off = nullptr;
@@ -664,7 +665,8 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
       case kAsm:
         hipLaunchKernelGGL(clsel::k_assemble, grid, dim3(256), 0, b->st,
                            (const clsel::AsmDesc*)dp, l.count, b->fronts, b->L.cfg_stride,
-                           b->d_front_sites, b->d_inv, b->links, b->linv, b->L.links_elems,
+                           b->d_front_sites, b->d_inv, (const uint32_t*)b->d_site_coords, b->links,
+                           b->linv, b->L.links_elems,
                            b->params, b->params + b->cap, ldims(P), b->iws, b->L.iws_elems);
         break;
       case kPanel:
@@ -787,7 +789,7 @@ void free_batch(cl_batch b) {
   hipFree(b->solve_blob); hipFree(b->rhs);
   if (b->lparams_host) hipHostFree(b->lparams_host);
   if (b->ev_lparam) hipEventDestroy(b->ev_lparam);
-  hipFree(b->d_front_sites); hipFree(b->d_inv); hipFree(b->d_rel); hipFree(b->d_sel_off);
+  hipFree(b->d_front_sites); hipFree(b->d_site_coords); hipFree(b->d_inv); hipFree(b->d_rel); hipFree(b->d_sel_off);
   hipFree(b->d_sel_ld);
   if (b->params_host) hipHostFree(b->params_host);
   for (hipEvent_t e : b->prof_ev) hipEventDestroy(e);
@@ -959,6 +961,7 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
   TRY(dalloc(&b->dblob, b->L.blob.size()));
   HTRY(hipMemcpy(b->dblob, b->L.blob.data(), b->L.blob.size(), hipMemcpyHostToDevice));
   TRY(upload(&b->d_front_sites, P.front_sites));
+  TRY(upload(&b->d_site_coords, P.site_coords));
   TRY(upload(&b->d_inv, P.inv_maps));
   TRY(upload(&b->d_rel, P.rel_maps));
   TRY(upload(&b->d_sel_off, P.sel_off));

@@ -97,7 +97,7 @@ def test_plan_flop_counts_8x8x8x4():
     assert info["flops_factor"] + info["flops_selinv"] >= alg * 0.99
 
 
-@pytest.mark.parametrize("dims", [(3, 4, 4, 4), (4, 4, 4, 2), (4, 4, 5, 4), (0, 4, 4, 4)])
+@pytest.mark.parametrize("dims", [(3, 4, 4, 4), (4, 4, 4, 2), (4, 4, 5, 4), (0, 4, 4, 4), (4, 256, 4, 4)])
 def test_symbolic_rejects_bad_extents(dims):
     with pytest.raises(clsel.ClselError) as e:
         Plan(dims)
