@@ -5,8 +5,8 @@
 // Each work-group computes a BM x BN complex tile (64 x 64, or 128 x 64 / 128 x 128)
 // with 4 waves (2 x 2), each wave a (BM/2) x (BN/2) tile made of TM x TN MFMA tiles of
 // 16 x 16 with two FP64 accumulators (real part fed by Ar*Br and (-Ai)*Bi, imaginary
-// part by Ar*Bi and Ai*Br). K advances BK complex per stage through LDS, real and
-// imaginary planes stored k-major so the MFMA operand reads are contiguous. Each
+// part by Ar*Bi and Ai*Br). K advances BK complex per stage through LDS, stored k-major
+// as complex pairs, so one 16-byte LDS read gives a lane both parts of its operand. Each
 // stage's global loads go to registers one stage ahead; with two LDS buffers (the
 // 64 x 64 tile, BK = 8) the registers are stored into the idle buffer right after the
 // current stage's MFMAs, so there is one barrier per stage and the kernel fits four
@@ -94,8 +94,8 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   const int row0 = (int)(tile / d.tiles_n) * BM;
   const int col0 = (int)(tile % d.tiles_n) * BN;
 
-  __shared__ double As[NBUF][2][BK][BM + 1];
-  __shared__ double Bs[NBUF][2][BK][BN + 1];
+  __shared__ double2 As[NBUF][BK][BM + 1];  // +1: the k-strided stores spread over banks
+  __shared__ double2 Bs[NBUF][BK][BN + 1];
   static_assert(BN <= kGemmThreads && kGemmThreads % BN == 0, "B load mapping");
 
   const int tid = threadIdx.x;
@@ -181,47 +181,32 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   };
   auto store_stage = [&](int buf) {
 #pragma unroll
-    for (int r = 0; r < RA; ++r) {
-      const int m = a_m0 + a_mstep * r;
-      As[buf][0][a_kk][m] = pa[r].x;
-      As[buf][1][a_kk][m] = pa[r].y;
-    }
+    for (int r = 0; r < RA; ++r) As[buf][a_kk][a_m0 + a_mstep * r] = pa[r];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      const int kk = b_kk0 + b_kstep * r;
-      Bs[buf][0][kk][b_n] = pb[r].x;
-      Bs[buf][1][kk][b_n] = pb[r].y;
-    }
+    for (int r = 0; r < RB; ++r) Bs[buf][b_kk0 + b_kstep * r][b_n] = pb[r];
   };
   auto mfma_stage = [&](int buf) {
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kk = 4 * k4 + l4;
-      double ar[TM], ai[TM], nai[TM], br[TN], bi[TN];
+      double2 av[TM], bv[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) {
-        ar[i] = As[buf][0][kk][wm * (BM / 2) + i * 16 + l16];
-        ai[i] = As[buf][1][kk][wm * (BM / 2) + i * 16 + l16];
-        nai[i] = -ai[i];
-      }
+      for (int i = 0; i < TM; ++i) av[i] = As[buf][kk][wm * (BM / 2) + i * 16 + l16];
 #pragma unroll
-      for (int j = 0; j < TN; ++j) {
-        br[j] = Bs[buf][0][kk][wn * (BN / 2) + j * 16 + l16];
-        bi[j] = Bs[buf][1][kk][wn * (BN / 2) + j * 16 + l16];
-      }
+      for (int j = 0; j < TN; ++j) bv[j] = Bs[buf][kk][wn * (BN / 2) + j * 16 + l16];
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, ci[i][j], 0, 0, 0);
         }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(nai[i], bi[j], cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], ci[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, ci[i][j], 0, 0, 0);
         }
     }
   };
