@@ -21,6 +21,8 @@
 // that step, written to the other pool with the step's row permutation applied.
 // Work-group ids are remapped so that each of the 8 XCDs (separate L2 caches) gets a
 // contiguous range of tiles, which share operand rows and columns.
+#include <type_traits>
+
 #include "desc.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
@@ -76,7 +78,7 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
 }
 
 template <int MODE, int TM, int TN, int BK, int NBUF>
-__global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : 2)
+__global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : (MODE < 2 ? 4 : 2))
 k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   constexpr int RA = BM * BK / kGemmThreads, RB = BN * BK / kGemmThreads;  // loads per thread per stage
@@ -130,7 +132,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   else if (MODE == 1) o.bbase = F + d.x_off;
   else o.bbase = W + d.rt_off;
 
-  auto ld_b = [&](int t) -> double2 {
+  auto ld_b = [&](int t) __attribute__((always_inline)) -> double2 {
     const double2 z = make_double2(0.0, 0.0);
     const int j = bcol;
     if (t >= d.K || j >= d.N) return z;
@@ -156,7 +158,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   // mode 2: the old front values that the update is subtracted from, loaded during the
   // last K stage so the loads overlap its MFMAs
   double2 base[TM][TN][4];
-  auto load_base = [&]() {
+  auto load_base = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -173,75 +175,96 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       }
   };
 
-  auto load_stage = [&](int k0) {
+  auto load_stage = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk);
 #pragma unroll
     for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + b_kk0 + b_kstep * r);
   };
-  auto store_stage = [&](int buf) {
+  auto store_stage = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < RA; ++r) As[buf][a_kk][a_m0 + a_mstep * r] = pa[r];
 #pragma unroll
     for (int r = 0; r < RB; ++r) Bs[buf][b_kk0 + b_kstep * r][b_n] = pb[r];
   };
-  auto mfma_stage = [&](int buf) {
+  // Tiles on the ragged edge of a front (sizes not multiples of the tile) skip the MFMAs
+  // of their 16 x 16 sub-tiles that lie wholly outside the problem. The test is uniform
+  // over a wave (the wave index goes through readfirstlane so that the compiler branches
+  // on scalars), and interior tiles run a copy of the pipeline without it.
+  const int wm_u = __builtin_amdgcn_readfirstlane(wm), wn_u = __builtin_amdgcn_readfirstlane(wn);
+  auto mfma_stage = [&](int buf, auto edge) __attribute__((always_inline)) {
+    constexpr bool EDGE = decltype(edge)::value;
+    bool rv[TM], cv[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) rv[i] = !EDGE || row0 + wm_u * (BM / 2) + i * 16 < d.M;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) cv[j] = !EDGE || col0 + wn_u * (BN / 2) + j * 16 < d.N;
 #pragma unroll
     for (int k4 = 0; k4 < BK / 4; ++k4) {
       const int kk = 4 * k4 + l4;
       double2 av[TM], bv[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) av[i] = As[buf][kk][wm * (BM / 2) + i * 16 + l16];
+      for (int i = 0; i < TM; ++i)
+        av[i] = rv[i] ? As[buf][kk][wm * (BM / 2) + i * 16 + l16] : make_double2(0.0, 0.0);
 #pragma unroll
-      for (int j = 0; j < TN; ++j) bv[j] = Bs[buf][kk][wn * (BN / 2) + j * 16 + l16];
+      for (int j = 0; j < TN; ++j)
+        bv[j] = cv[j] ? Bs[buf][kk][wn * (BN / 2) + j * 16 + l16] : make_double2(0.0, 0.0);
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, ci[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < TN; ++j)
+          if (rv[i] && cv[j]) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, ci[i][j], 0, 0, 0);
+          }
 #pragma unroll
       for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, ci[i][j], 0, 0, 0);
-        }
+        for (int j = 0; j < TN; ++j)
+          if (rv[i] && cv[j]) {
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, ci[i][j], 0, 0, 0);
+          }
     }
   };
 
   const int nst = (d.K + BK - 1) / BK;
-  load_stage(0);
-  if (NBUF == 1) {
-    // one buffer: store the prefetched stage, prefetch the next, MFMAs, two barriers
-    for (int st = 0; st + 1 < nst; ++st) {
+  auto pipeline = [&](auto edge) __attribute__((always_inline)) {
+    load_stage(0);
+    if (NBUF == 1) {
+      // one buffer: store the prefetched stage, prefetch the next, MFMAs, two barriers
+      for (int st = 0; st + 1 < nst; ++st) {
+        store_stage(0);
+        __syncthreads();
+        load_stage((st + 1) * BK);
+        mfma_stage(0, edge);
+        __syncthreads();
+      }
       store_stage(0);
       __syncthreads();
-      load_stage((st + 1) * BK);
-      mfma_stage(0);
+      // mode 2 fetches its subtrahend during the last stage so the loads overlap the MFMAs
+      if (MODE == 2) load_base();
+      mfma_stage(0, edge);
+    } else {
+      // two buffers: stage st+1 goes into the idle buffer after stage st's MFMAs (that
+      // buffer was last read in stage st-1, before the previous barrier): one barrier
+      store_stage(0);
       __syncthreads();
+      if (nst > 1) load_stage(BK);
+      for (int st = 0; st + 1 < nst; ++st) {
+        mfma_stage(st & 1, edge);
+        store_stage((st + 1) & 1);
+        if (st + 2 < nst) load_stage((st + 2) * BK);
+        __syncthreads();
+      }
+      if (MODE == 2) load_base();
+      mfma_stage((nst - 1) & 1, edge);
     }
-    store_stage(0);
-    __syncthreads();
-    // mode 2 fetches its subtrahend during the last stage so the loads overlap the MFMAs
-    if (MODE == 2) load_base();
-    mfma_stage(0);
-  } else {
-    // two buffers: stage st+1 goes into the idle buffer after stage st's MFMAs (that
-    // buffer was last read in stage st-1, before the previous barrier): one barrier
-    store_stage(0);
-    __syncthreads();
-    if (nst > 1) load_stage(BK);
-    for (int st = 0; st + 1 < nst; ++st) {
-      mfma_stage(st & 1);
-      store_stage((st + 1) & 1);
-      if (st + 2 < nst) load_stage((st + 2) * BK);
-      __syncthreads();
-    }
-    if (MODE == 2) load_base();
-    mfma_stage((nst - 1) & 1);
-  }
+  };
+  // (mode 1 has at most one pivot block of rows; its edge copy would not fit four waves)
+  if constexpr (MODE == 1) pipeline(std::false_type{});
+  else if (row0 + BM <= d.M && col0 + BN <= d.N) pipeline(std::false_type{});
+  else pipeline(std::true_type{});
 
 #pragma unroll
   for (int i = 0; i < TM; ++i)
