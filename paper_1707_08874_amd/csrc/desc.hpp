@@ -21,7 +21,7 @@ struct AsmDesc {
   int64_t off;            // front offset: update rows are assembled into pool 0
   int64_t joff;           // front offset incl. pool for the pivot rows
   int64_t site_off;       // into front_sites
-  int64_t blk_start;      // first 256-element block of this front in the launch
+  int64_t blk_start;      // first 8 x 256 tile of this front in the launch (row-major tiles)
   int H, p, ld, nchild;
   int64_t inv_off[4];     // per child: H entries (parent row -> child update row)
   int64_t child_off[4];   // child front offset, already including its pool
@@ -68,7 +68,7 @@ struct GatherDesc {
   int64_t z_off;          // this front's Z front (incl. pool)
   int64_t par_off;        // parent's Z front (incl. pool)
   int64_t rel_off;        // s entries
-  int64_t blk_start;
+  int64_t blk_start;      // first 8 x 256 tile of Z_SS of this front in the launch
   int p, s, ld, par_ld;
 };
 

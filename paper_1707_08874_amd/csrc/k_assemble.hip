@@ -76,9 +76,11 @@ __device__ __forceinline__ double2 dirac_entry(int x, int a, int y, int b, uint3
   return make_double2(0.0, 0.0);
 }
 
-// One thread per front element. Front entry (I, J) = sum over children of the
-// child's update block at the mapped position + the entry of D if row I or column J
-// is a pivot of this front (entries between two update rows belong to ancestors).
+// One work-group per 8 x 256 tile of a front; each thread takes one column of the tile. Front entry (I, J) = sum over children of the child's update
+// block at the mapped position + the entry of D if row I or column J is a pivot of
+// this front (entries between two update rows belong to ancestors). What depends on
+// the column (child maps, site, coordinates) is read once per lane; what depends on the
+// row is uniform over the work-group.
 __global__ void __launch_bounds__(256)
 k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ fronts,
            int64_t cfg_stride, const int32_t* __restrict__ front_sites,
@@ -87,6 +89,7 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
            const double2* __restrict__ linv, int64_t link_cfg_stride,
            const double* __restrict__ mvals, const double* __restrict__ muvals, LatticeDims dims,
            int32_t* __restrict__ iws, int64_t iws_stride) {
+  constexpr int kRows = kAsmTileRows;
   const int b = blockIdx.y;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {  // last desc with blk_start <= blockIdx.x
@@ -94,29 +97,56 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     if (descs[mid].blk_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
   }
   const AsmDesc& d = descs[lo];
-  // H <= 16383, so H*H and every element index fit in 32 bits (cheap division)
-  const int e = (int)((int64_t)blockIdx.x - d.blk_start) * 256 + (int)threadIdx.x;
-  if (e >= d.H * d.H) return;
-  const int I = e / d.H, J = e - (e / d.H) * d.H;
+  const int t = (int)((int64_t)blockIdx.x - d.blk_start);
+  const int tn = (d.H + kAsmTileCols - 1) / kAsmTileCols;
+  const int tr = t / tn, tc = t - tr * tn;
+  const int J = tc * kAsmTileCols + (int)threadIdx.x;
+  const int I0 = tr * kAsmTileRows;
+  if (J >= d.H || I0 >= d.H) return;  // no barriers below
+
   double2* F = fronts + b * cfg_stride;
-  double2 v = make_double2(0.0, 0.0);
-  for (int c = 0; c < d.nchild; ++c) {
-    const int ii = inv_maps[d.inv_off[c] + I];
-    const int jj = inv_maps[d.inv_off[c] + J];
-    if (ii >= 0 && jj >= 0) {
-      const int cp = d.child_p[c];
-      v = cadd(v, F[d.child_off[c] + (int64_t)(cp + ii) * d.child_ld[c] + cp + jj]);
+  const double2* U = links + b * link_cfg_stride;
+  const double2* Ui = linv + b * link_cfg_stride;
+  const double m = mvals[b], mu = muvals[b];
+  const int nchild = d.nchild;
+  int jj[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) jj[c] = c < nchild ? inv_maps[d.inv_off[c] + J] : -1;
+  const bool jpiv = J < d.p;
+  const int y = front_sites[d.site_off + J / 3];
+  const uint32_t py = site_coords[y];
+  const int bj = J % 3;
+
+  // the children's contributions of all rows first, so that their loads are in flight
+  // together; then the entries of D and the stores
+  const int rows = min(kRows, d.H - I0);
+  double2 v[kRows];
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) v[k] = make_double2(0.0, 0.0);
+  for (int c = 0; c < nchild; ++c) {
+    const int cp = d.child_p[c];
+    const double2* C = F + d.child_off[c] + cp + jj[c];
+    double2 w[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int ii = k < rows ? inv_maps[d.inv_off[c] + I0 + k] : -1;
+      w[k] = ii >= 0 && jj[c] >= 0 ? C[(int64_t)(cp + ii) * d.child_ld[c]] : make_double2(0.0, 0.0);
     }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) v[k] = cadd(v[k], w[k]);
   }
-  if (I < d.p || J < d.p) {
-    const int x = front_sites[d.site_off + I / 3];
-    const int y = front_sites[d.site_off + J / 3];
-    v = cadd(v, dirac_entry(x, I % 3, y, J % 3, site_coords[x], site_coords[y],
-                            links + b * link_cfg_stride, linv + b * link_cfg_stride, mvals[b],
-                            muvals[b], dims));
+#pragma unroll
+  for (int k = 0; k < kRows; ++k) {
+    if (k >= rows) break;
+    const int I = I0 + k;
+    const bool ipiv = I < d.p;
+    if (ipiv || jpiv) {
+      const int x = front_sites[d.site_off + I / 3];
+      v[k] = cadd(v[k], dirac_entry(x, I % 3, y, bj, site_coords[x], py, U, Ui, m, mu, dims));
+    }
+    F[(ipiv ? d.joff : d.off) + (int64_t)I * d.ld + J] = v[k];
   }
-  F[(I < d.p ? d.joff : d.off) + (int64_t)I * d.ld + J] = v;
-  if (e < d.p) iws[b * iws_stride + d.rowid_off + e] = (int32_t)e;
+  if (I0 == 0 && jpiv) iws[b * iws_stride + d.rowid_off + J] = J;
 }
 
 }  // namespace clsel

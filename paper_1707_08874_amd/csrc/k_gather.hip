@@ -11,6 +11,7 @@ namespace clsel {
 __global__ void __launch_bounds__(256)
 k_gather_zss(const GatherDesc* __restrict__ descs, int ndesc, double2* __restrict__ fronts,
              int64_t cfg_stride, const int32_t* __restrict__ rel_maps) {
+  constexpr int kRows = kAsmTileRows;
   const int b = blockIdx.y;
   int lo = 0, hi = ndesc - 1;
   while (lo < hi) {
@@ -18,12 +19,30 @@ k_gather_zss(const GatherDesc* __restrict__ descs, int ndesc, double2* __restric
     if (descs[mid].blk_start <= (int64_t)blockIdx.x) lo = mid; else hi = mid - 1;
   }
   const GatherDesc& d = descs[lo];
-  const int e = (int)((int64_t)blockIdx.x - d.blk_start) * 256 + (int)threadIdx.x;
-  if (e >= d.s * d.s) return;
-  const int a = e / d.s, c = e - (e / d.s) * d.s;
+  // one work-group per 8 x 256 tile of Z_SS, one column per thread
+  const int t = (int)((int64_t)blockIdx.x - d.blk_start);
+  const int tn = (d.s + kAsmTileCols - 1) / kAsmTileCols;
+  const int tr = t / tn, tc = t - tr * tn;
+  const int c = tc * kAsmTileCols + (int)threadIdx.x;
+  const int a0 = tr * kAsmTileRows;
+  if (c >= d.s || a0 >= d.s) return;
   double2* F = fronts + b * cfg_stride;
-  const int ra = rel_maps[d.rel_off + a], rc = rel_maps[d.rel_off + c];
-  F[d.z_off + (int64_t)(d.p + a) * d.ld + d.p + c] = F[d.par_off + (int64_t)ra * d.par_ld + rc];
+  const double2* src = F + d.par_off + rel_maps[d.rel_off + c];
+  double2* dst = F + d.z_off + (int64_t)(d.p + a0) * d.ld + d.p + c;
+  const int rows = min(kRows, d.s - a0);
+  if (rows == kRows) {  // the eight loads in flight together, then the stores
+    double vr[kRows], vi[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const double2 t = src[(int64_t)rel_maps[d.rel_off + a0 + k] * d.par_ld];
+      vr[k] = t.x;
+      vi[k] = t.y;
+    }
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) dst[(int64_t)k * d.ld] = make_double2(vr[k], vi[k]);
+  } else {
+    for (int k = 0; k < rows; ++k) dst[(int64_t)k * d.ld] = src[(int64_t)rel_maps[d.rel_off + a0 + k] * d.par_ld];
+  }
 }
 
 // Selected blocks on the pattern of D: out[b][x][slot][3][3], slot 0 = (x,x),

@@ -122,7 +122,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       d.joff = fr.jbuf * pool + fr.off;
       d.site_off = fr.site_off;
       d.blk_start = blk;
-      blk += cdiv64((int64_t)fr.H * fr.H, 256);
+      blk += cdiv64(fr.H, clsel::kAsmTileRows) * cdiv64(fr.H, clsel::kAsmTileCols);
       d.H = fr.H; d.p = fr.p; d.ld = fr.ld; d.nchild = fr.nchild;
       for (int c = 0; c < fr.nchild; ++c) {
         const clsel::Front& ch = P.fronts[fr.child[c]];
@@ -233,7 +233,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       g.par_off = par.zbuf * pool + par.off;
       g.rel_off = fr.rel_off;
       g.blk_start = blk;
-      blk += cdiv64((int64_t)fr.s * fr.s, 256);
+      blk += cdiv64(fr.s, clsel::kAsmTileRows) * cdiv64(fr.s, clsel::kAsmTileCols);
       g.p = fr.p; g.s = fr.s; g.ld = fr.ld; g.par_ld = par.ld;
       gd.push_back(g);
       const int zp = fr.zbuf, fp = fr.fbuf, ld = fr.ld;
@@ -310,8 +310,8 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
       int64_t blk = 0;
       for (int i = 0; i < l.count; ++i) {
         REQ(d[i].blk_start == blk, "asm block start", d[i].blk_start, blk);
-        blk += cdiv64((int64_t)d[i].H * d[i].H, 256);
-        REQ((int64_t)d[i].H * d[i].H < (int64_t(1) << 31), "asm 32-bit element index", d[i].H, 46340);
+        blk += cdiv64(d[i].H, clsel::kAsmTileRows) * cdiv64(d[i].H, clsel::kAsmTileCols);
+        REQ(d[i].nchild >= 0 && d[i].nchild <= 4, "asm children", d[i].nchild, 4);
         REQ(d[i].off + (int64_t)d[i].H * d[i].ld <= pool, "asm front", d[i].off, pool);
         REQ(d[i].joff + (int64_t)d[i].p * d[i].ld <= two, "asm pivot rows", d[i].joff, two);
         REQ(d[i].site_off + d[i].H / 3 <= (int64_t)P.front_sites.size(), "asm sites", d[i].site_off, 0);
@@ -377,15 +377,18 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
   for (const Launch& l : L.selinv) {
     if (l.kind != kZss) continue;
     const clsel::GatherDesc* d = (const clsel::GatherDesc*)(L.blob.data() + l.desc_off);
+    int64_t blk = 0;
     for (int i = 0; i < l.count; ++i) {
       const int64_t H = d[i].p + d[i].s;
-      REQ((int64_t)d[i].s * d[i].s < (int64_t(1) << 31), "gather 32-bit element index", d[i].s, 46340);
+      REQ(d[i].blk_start == blk, "gather block start", d[i].blk_start, blk);
+      blk += cdiv64(d[i].s, clsel::kAsmTileRows) * cdiv64(d[i].s, clsel::kAsmTileCols);
       REQ(d[i].z_off + H * d[i].ld <= two, "gather front", d[i].z_off, two);
       REQ(d[i].rel_off + d[i].s <= (int64_t)P.rel_maps.size(), "gather rel", d[i].rel_off, 0);
       int64_t mx = 0;
       for (int a = 0; a < d[i].s; ++a) mx = std::max<int64_t>(mx, P.rel_maps[d[i].rel_off + a]);
       REQ(d[i].par_off + mx * d[i].par_ld + mx < two, "gather parent", d[i].par_off, two);
     }
+    REQ(blk == l.gridx, "gather grid", blk, l.gridx);
   }
   for (size_t i = 0; i < P.sel_off.size(); ++i)
     REQ(P.sel_off[i] + 2 * (int64_t)P.sel_ld[i] + 2 < two && P.sel_off[i] >= 0, "selected offset", P.sel_off[i], two);
