@@ -155,6 +155,37 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 
   double2 pa[RA], pb[RB];
 
+  // Each wave owns TM x TN accumulator slots of 16 x 16. In an interior tile slot (i, j)
+  // is the sub-tile (2 wm + i, 2 wn + j) of the wave's quadrant. A tile on the ragged edge
+  // of a front (sizes not multiples of the tile) has only vr x vc sub-tiles inside the
+  // product, and skips the MFMAs of the others. In mode 0 (long K) they are dealt
+  // round-robin to the four waves (sub-tile s to wave s % 4), so that all four SIMDs get
+  // an equal share and the tile finishes sooner; mode 2 (K = one block) keeps the
+  // quadrants, whose shared fragments and row pointers suit its short loop. Slots are
+  // uniform over a wave (the wave index goes through readfirstlane, so the compiler
+  // keeps them in scalar registers and branches on scalars).
+  constexpr int kSlots = TM * TN;
+  constexpr bool kRoundRobin = MODE == 0;
+  const bool interior = row0 + BM <= d.M && col0 + BN <= d.N;
+  const int wave_u = __builtin_amdgcn_readfirstlane(wave);
+  const int vr = (min(BM, d.M - row0) + 15) / 16, vc = (min(BN, d.N - col0) + 15) / 16;
+  int srow[kSlots], scol[kSlots];
+  bool sok[kSlots];
+#pragma unroll
+  for (int t = 0; t < kSlots; ++t) {
+    if (interior || !kRoundRobin) {
+      const int qi = (wave_u >> 1) * TM + t / TN, qj = (wave_u & 1) * TN + t % TN;
+      srow[t] = qi * 16;
+      scol[t] = qj * 16;
+      sok[t] = interior || (qi < vr && qj < vc);
+    } else {
+      const int sub = wave_u + 4 * t;
+      sok[t] = sub < vr * vc;
+      srow[t] = (sub / vc) * 16;
+      scol[t] = (sub % vc) * 16;
+    }
+  }
+
   // mode 2: the old front values that the update is subtracted from, loaded during the
   // last K stage so the loads overlap its MFMAs
   double2 base[TM][TN][4];
@@ -187,44 +218,84 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) Bs[buf][b_kk0 + b_kstep * r][b_n] = pb[r];
   };
-  // Tiles on the ragged edge of a front (sizes not multiples of the tile) skip the MFMAs
-  // of their 16 x 16 sub-tiles that lie wholly outside the problem. The test is uniform
-  // over a wave (the wave index goes through readfirstlane so that the compiler branches
-  // on scalars), and interior tiles run a copy of the pipeline without it.
-  const int wm_u = __builtin_amdgcn_readfirstlane(wm), wn_u = __builtin_amdgcn_readfirstlane(wn);
   auto mfma_stage = [&](int buf, auto edge) __attribute__((always_inline)) {
-    constexpr bool EDGE = decltype(edge)::value;
-    bool rv[TM], cv[TN];
+    if constexpr (!decltype(edge)::value) {
+      // interior: a 2 x 2 block of sub-tiles shares its A and B fragments
 #pragma unroll
-    for (int i = 0; i < TM; ++i) rv[i] = !EDGE || row0 + wm_u * (BM / 2) + i * 16 < d.M;
+      for (int k4 = 0; k4 < BK / 4; ++k4) {
+        const int kk = 4 * k4 + l4;
+        double2 av[TM], bv[TN];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) cv[j] = !EDGE || col0 + wn_u * (BN / 2) + j * 16 < d.N;
+        for (int i = 0; i < TM; ++i) av[i] = As[buf][kk][wm * (BM / 2) + i * 16 + l16];
 #pragma unroll
-    for (int k4 = 0; k4 < BK / 4; ++k4) {
-      const int kk = 4 * k4 + l4;
-      double2 av[TM], bv[TN];
+        for (int j = 0; j < TN; ++j) bv[j] = Bs[buf][kk][wn * (BN / 2) + j * 16 + l16];
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
-        av[i] = rv[i] ? As[buf][kk][wm * (BM / 2) + i * 16 + l16] : make_double2(0.0, 0.0);
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-      for (int j = 0; j < TN; ++j)
-        bv[j] = cv[j] ? Bs[buf][kk][wn * (BN / 2) + j * 16 + l16] : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-          if (rv[i] && cv[j]) {
+          for (int j = 0; j < TN; ++j) {
             cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, cr[i][j], 0, 0, 0);
             ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, ci[i][j], 0, 0, 0);
           }
 #pragma unroll
-      for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-          if (rv[i] && cv[j]) {
+          for (int j = 0; j < TN; ++j) {
             cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, cr[i][j], 0, 0, 0);
             ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, ci[i][j], 0, 0, 0);
           }
+      }
+    } else if constexpr (!kRoundRobin) {
+      // edge, quadrant slots: fragments of sub-tiles outside the product are not read
+      bool rv[TM], cv[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) rv[i] = sok[i * TN];
+#pragma unroll
+      for (int j = 0; j < TN; ++j) cv[j] = (wave_u & 1) * TN + j < vc;
+#pragma unroll
+      for (int k4 = 0; k4 < BK / 4; ++k4) {
+        const int kk = 4 * k4 + l4;
+        double2 av[TM], bv[TN];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+          av[i] = rv[i] ? As[buf][kk][wm * (BM / 2) + i * 16 + l16] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          bv[j] = cv[j] ? Bs[buf][kk][wn * (BN / 2) + j * 16 + l16] : make_double2(0.0, 0.0);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (sok[i * TN + j]) {
+              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].x, cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].x, bv[j].y, ci[i][j], 0, 0, 0);
+            }
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+          for (int j = 0; j < TN; ++j)
+            if (sok[i * TN + j]) {
+              cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[i].y, bv[j].y, cr[i][j], 0, 0, 0);
+              ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i].y, bv[j].x, ci[i][j], 0, 0, 0);
+            }
+      }
+    } else {
+      // edge, round-robin slots: each owned sub-tile reads its own fragments
+#pragma unroll
+      for (int k4 = 0; k4 < BK / 4; ++k4) {
+        const int kk = 4 * k4 + l4;
+#pragma unroll
+        for (int t = 0; t < kSlots; ++t) {
+          if (!sok[t]) continue;
+          const double2 a = As[buf][kk][srow[t] + l16];
+          const double2 bb = Bs[buf][kk][scol[t] + l16];
+          d4& xr = cr[t / TN][t % TN];
+          d4& xi = ci[t / TN][t % TN];
+          xr = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bb.x, xr, 0, 0, 0);
+          xi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.x, bb.y, xi, 0, 0, 0);
+          xr = __builtin_amdgcn_mfma_f64_16x16x4f64(-a.y, bb.y, xr, 0, 0, 0);
+          xi = __builtin_amdgcn_mfma_f64_16x16x4f64(a.y, bb.x, xi, 0, 0, 0);
+        }
+      }
     }
   };
 
@@ -261,9 +332,10 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       mfma_stage((nst - 1) & 1, edge);
     }
   };
-  // (mode 1 has at most one pivot block of rows; its edge copy would not fit four waves)
+  // (mode 1 has at most one pivot block of rows; its edge copy would not fit four waves,
+  // and its edge tiles run the interior copy, which computes every sub-tile)
   if constexpr (MODE == 1) pipeline(std::false_type{});
-  else if (row0 + BM <= d.M && col0 + BN <= d.N) pipeline(std::false_type{});
+  else if (interior) pipeline(std::false_type{});
   else pipeline(std::true_type{});
 
 #pragma unroll
@@ -272,9 +344,11 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * (BM / 2) + i * 16 + 4 * r + l4;
-        const int col = col0 + wn * (BN / 2) + j * 16 + l16;
-        if (row >= d.M || col >= d.N) continue;
+        const int t = i * TN + j;
+        // mode 1 runs the interior mapping on every tile
+        const int row = row0 + (MODE == 1 ? wm * (BM / 2) + i * 16 : srow[t]) + 4 * r + l4;
+        const int col = col0 + (MODE == 1 ? wn * (BN / 2) + j * 16 : scol[t]) + l16;
+        if ((MODE != 1 && !sok[t]) || row >= d.M || col >= d.N) continue;
         const double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
         if (MODE == 0) {
           double2 v = cscale(acc, d.alpha);
