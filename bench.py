@@ -61,6 +61,9 @@ def main():
     ap.add_argument("--langevin", action="store_true",
                     help="complex Langevin steps (exact fermion drift + gauge drift + update) on the "
                          "batched workload")
+    ap.add_argument("--library-gemm", action="store_true",
+                    help="each mode-0 GEMM launch of the batched step (kernel time from HIP events) "
+                         "beside the library's batched complex128 GEMM (torch.bmm) on the same problems")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     args = ap.parse_args()
@@ -81,6 +84,8 @@ def main():
         return langevin(args)
     if args.stochastic:
         return stochastic(args)
+    if args.library_gemm:
+        return library_gemm(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -242,6 +247,87 @@ def main():
         "status_ok": bool((status == 0).all()),
     }
     print(json.dumps(out))
+
+
+def _gemm_launch_labels(plan, nb):
+    """Mode and name of every GEMM launch of one run, in launch order: per level of the
+    factorisation the block steps (mode 1, mode 2) then the Schur launch (mode 0); then the
+    selected inversion from the root level down (two mode-0 launches per level)."""
+    fr = plan.fronts()
+    levels = sorted(set(f["level"] for f in fr))
+    out = []
+    for lev in levels:
+        fs = [f for f in fr if f["level"] == lev]
+        for _q in range(max(-(-f["p"] // nb) for f in fs)):
+            out += [(1, f"L{lev} step"), (2, f"L{lev} step")]
+        if any(f["s"] > 0 for f in fs):
+            out.append((0, f"L{lev} Schur"))
+    for lev in reversed(levels):
+        if any(f["s"] > 0 for f in fr if f["level"] == lev):
+            out += [(0, f"L{lev} selinv A"), (0, f"L{lev} selinv B")]
+    return out
+
+
+def library_gemm(args):
+    """Mode-0 launches of the batched step against torch.bmm (the ROCm library's batched
+    complex128 GEMM) over the same problems, one JSON line per launch."""
+    import numpy as np
+    import torch
+
+    from paper_1707_08874_amd import autotune, clsel
+    from paper_1707_08874_amd.inputs import gen_batch
+    dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
+    opts = autotune.options(dims, B)
+    plan = clsel.Plan(dims, **opts)
+    labels = _gemm_launch_labels(plan, opts["nb"])
+    lt = torch.from_numpy(gen_batch(dims, range(B))).to("cuda")
+    b = clsel.Batch(plan, B)
+    b.run(lt, m, mu)
+    b.sync()
+    b.profile(7)
+    b.run(lt, m, mu)
+    b.sync()
+    d = b.profile_launches()
+    b.profile_read()
+    b.profile(0)
+    b.close()
+    if [mm for mm, _ in labels] != list(d["mode"]):
+        raise RuntimeError("launch order differs from the plan's levels")
+    fr = plan.fronts()
+    for (mode, name), ms, fl in zip(labels, d["ms"], d["flops"]):
+        if mode != 0:
+            continue
+        lev = int(name.split()[0][1:])
+        fs = [f for f in fr if f["level"] == lev and f["s"] > 0]
+        probs = {}
+        for f in fs:
+            p_, s_ = f["p"], f["s"]
+            if name.endswith("Schur"):
+                mnk = [(s_, s_, p_), (s_, p_, p_)]
+            elif name.endswith("A"):
+                mnk = [(s_, p_, s_), (p_, s_, s_)]
+            else:
+                mnk = [(p_, p_, s_)]
+            for t in mnk:
+                probs[t] = probs.get(t, 0) + B
+        lib_ms = 0.0
+        for (M, N, K), cnt in probs.items():
+            x = torch.randn(cnt, M, K, dtype=torch.complex128, device="cuda")
+            y = torch.randn(cnt, K, N, dtype=torch.complex128, device="cuda")
+            torch.bmm(x, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(3):
+                torch.bmm(x, y)
+            e1.record()
+            torch.cuda.synchronize()
+            lib_ms += e0.elapsed_time(e1) / 3
+            del x, y
+        print(json.dumps({"launch": name, "problems": {f"{M}x{N}x{K}": c for (M, N, K), c in probs.items()},
+                          "gflop": fl / 1e9, "kernel_ms": ms, "kernel_tflops": fl / ms / 1e9,
+                          "library_ms": lib_ms, "library_tflops": fl / lib_ms / 1e9}), flush=True)
+    return 0
 
 
 def stochastic(args):

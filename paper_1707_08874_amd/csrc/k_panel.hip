@@ -213,28 +213,41 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
                                          : PW[(int64_t)pr * nbk + rest0 + cc];
       }
       __syncthreads();
-      constexpr int kChunk = RPT >= 2 ? 4 : 8;  // independent loads in flight per row
+      // the loads of a chunk of columns of all RPT rows are issued together, so that
+      // 8 * RPT loads per thread are in flight before the first product needs one
+      constexpr int kChunk = 8;
+      for (int c0 = 0; c0 < nrest; c0 += kChunk) {
+        double2 acc[RPT][kChunk];
 #pragma unroll
-      for (int j = 0; j < RPT; ++j) {
-        const int r = tid + j * kPanelThreads;
-        if (r < cand && !used[j]) {
+        for (int j = 0; j < RPT; ++j) {
+          const int r = tid + j * kPanelThreads;
+          const bool ok = r < cand && !used[j];
           const double2* src = g0 == 0 ? Xp + (int64_t)r * ld + rest0 : PW + (int64_t)r * nbk + rest0;
-          double2* dst = PW + (int64_t)r * nbk + rest0;
-          for (int c0 = 0; c0 < nrest; c0 += kChunk) {
-            double2 acc[kChunk];
 #pragma unroll
-            for (int q = 0; q < kChunk; ++q)
-              acc[q] = (c0 + q < nrest) ? src[c0 + q] : make_double2(0.0, 0.0);
+          for (int q = 0; q < kChunk; ++q)
+            acc[j][q] = (ok && c0 + q < nrest) ? src[c0 + q] : make_double2(0.0, 0.0);
+        }
+        // each pivot-row value is read from LDS once per chunk and used for all RPT rows
+        // (the sum over t runs in the same order for every element)
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+          if (t < gw) {
 #pragma unroll
             for (int q = 0; q < kChunk; ++q) {
-              const int cc = c0 + q;
-              if (cc < nrest) {
+              const double2 rv = s_buf[t * kMaxNB + min(c0 + q, nrest - 1)];
 #pragma unroll
-                for (int t = 0; t < kGroup; ++t)
-                  if (t < gw) acc[q] = cfma(acc[q], cur[j][t], s_buf[t * kMaxNB + cc]);
-                dst[cc] = acc[q];
-              }
+              for (int j = 0; j < RPT; ++j) acc[j][q] = cfma(acc[j][q], cur[j][t], rv);
             }
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < RPT; ++j) {
+          const int r = tid + j * kPanelThreads;
+          if (r < cand && !used[j]) {
+            double2* dst = PW + (int64_t)r * nbk + rest0;
+#pragma unroll
+            for (int q = 0; q < kChunk; ++q)
+              if (c0 + q < nrest) dst[c0 + q] = acc[j][q];
           }
         }
       }
