@@ -327,6 +327,21 @@ def library_gemm(args):
         print(json.dumps({"launch": name, "problems": {f"{M}x{N}x{K}": c for (M, N, K), c in probs.items()},
                           "gflop": fl / 1e9, "kernel_ms": ms, "kernel_tflops": fl / ms / 1e9,
                           "library_ms": lib_ms, "library_tflops": fl / lib_ms / 1e9}), flush=True)
+    # the library on large square products, for the ceiling of its batched complex GEMM
+    x = torch.randn(4, 4096, 4096, dtype=torch.complex128, device="cuda")
+    y = torch.randn(4, 4096, 4096, dtype=torch.complex128, device="cuda")
+    torch.bmm(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(3):
+        torch.bmm(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 3
+    fl = 8.0 * 4 * 4096 ** 3
+    print(json.dumps({"launch": "library reference", "problems": {"4096x4096x4096": 4}, "gflop": fl / 1e9,
+                      "library_ms": ms, "library_tflops": fl / ms / 1e9}), flush=True)
     return 0
 
 
