@@ -16,7 +16,9 @@ namespace clsel {
 // Pool selectors for plain GEMM operands.
 enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2, kPoolRhs = 3 };
 
-// Front assembly: one entry per (front) of a level.
+// Front assembly: one entry per (front) of a level. Entries between two update rows
+// (the S x S block) are left to the Schur-complement GEMM, which sums the children's
+// contributions to them itself.
 struct AsmDesc {
   int64_t off;            // front offset: update rows are assembled into pool 0
   int64_t joff;           // front offset incl. pool for the pivot rows
@@ -54,7 +56,14 @@ struct GemmDesc {
   int64_t a_off, b_off, c_off, c0_off;
   int lda, ldb, ldc, ldc0;
   double alpha;
-  int has_c0;
+  int has_c0;             // 0: none; 1: C0 at c0_off; 2: the children's update blocks (below)
+  // has_c0 = 2 (Schur complement S = A_SS - A_SJ U^): A_SS is the sum over the children
+  // of their update blocks at the mapped positions, read here instead of from an
+  // assembled copy. Output (row, col) is front entry (kid_base + row, kid_base + col).
+  int nchild, kid_base;
+  int child_p[4], child_ld[4];
+  int64_t inv_off[4];     // per child: front row -> child update row (-1: none)
+  int64_t child_off[4];   // child front offset, including its pool
   // modes 1, 2
   int k, nbk, p, ld, last;
   int64_t x_off, y_off;   // input / output front (incl. pool)

@@ -76,11 +76,13 @@ __device__ __forceinline__ double2 dirac_entry(int x, int a, int y, int b, uint3
   return make_double2(0.0, 0.0);
 }
 
-// One work-group per 8 x 256 tile of a front; each thread takes one column of the tile. Front entry (I, J) = sum over children of the child's update
-// block at the mapped position + the entry of D if row I or column J is a pivot of
-// this front (entries between two update rows belong to ancestors). What depends on
-// the column (child maps, site, coordinates) is read once per lane; what depends on the
-// row is uniform over the work-group.
+// One work-group per 8 x 256 tile of a front; each thread takes one column of the tile.
+// Front entry (I, J) with row I or column J a pivot of this front = sum over children of
+// the child's update block at the mapped position + the entry of D. Entries between two
+// update rows are not written: their D entries belong to ancestors, and the Schur-
+// complement GEMM of this front sums the children's contributions to them itself. What
+// depends on the column (child maps, site, coordinates) is read once per thread; what
+// depends on the row is uniform over the work-group.
 __global__ void __launch_bounds__(256)
 k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ fronts,
            int64_t cfg_stride, const int32_t* __restrict__ front_sites,
@@ -102,7 +104,9 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
   const int tr = t / tn, tc = t - tr * tn;
   const int J = tc * kAsmTileCols + (int)threadIdx.x;
   const int I0 = tr * kAsmTileRows;
-  if (J >= d.H || I0 >= d.H) return;  // no barriers below
+  // entries between two update rows (the S x S block) are the Schur GEMM's: it sums the
+  // children's contributions to them itself
+  if (J >= d.H || I0 >= d.H || (I0 >= d.p && J >= d.p)) return;  // no barriers below
 
   double2* F = fronts + b * cfg_stride;
   const double2* U = links + b * link_cfg_stride;
@@ -129,7 +133,7 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     double2 w[kRows];
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
-      const int ii = k < rows ? inv_maps[d.inv_off[c] + I0 + k] : -1;
+      const int ii = k < rows && (jpiv || I0 + k < d.p) ? inv_maps[d.inv_off[c] + I0 + k] : -1;
       w[k] = ii >= 0 && jj[c] >= 0 ? C[(int64_t)(cp + ii) * d.child_ld[c]] : make_double2(0.0, 0.0);
     }
 #pragma unroll
@@ -140,10 +144,9 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     if (k >= rows) break;
     const int I = I0 + k;
     const bool ipiv = I < d.p;
-    if (ipiv || jpiv) {
-      const int x = front_sites[d.site_off + I / 3];
-      v[k] = cadd(v[k], dirac_entry(x, I % 3, y, bj, site_coords[x], py, U, Ui, m, mu, dims));
-    }
+    if (!ipiv && !jpiv) continue;
+    const int x = front_sites[d.site_off + I / 3];
+    v[k] = cadd(v[k], dirac_entry(x, I % 3, y, bj, site_coords[x], py, U, Ui, m, mu, dims));
     F[(ipiv ? d.joff : d.off) + (int64_t)I * d.ld + J] = v[k];
   }
   if (I0 == 0 && jpiv) iws[b * iws_stride + d.rowid_off + J] = J;

@@ -44,6 +44,7 @@ struct GemmCtx {
   int64_t iws_stride;
   double2* rhs;         // right-hand-side workspace of the solves (pool kPoolRhs)
   int64_t rhs_stride;
+  const int32_t* inv_maps;  // plan: front row -> child update row (Schur with has_c0 = 2)
 };
 
 __device__ __forceinline__ double2* pool_ptr(const GemmCtx& g, int b, int pool) {
@@ -352,7 +353,22 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
         const double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
         if (MODE == 0) {
           double2 v = cscale(acc, d.alpha);
-          if (d.has_c0) v = cadd(v, pool_ptr(g, b, d.c0_pool)[d.c0_off + (int64_t)row * d.ldc0 + col]);
+          if (d.has_c0 == 1) {
+            v = cadd(v, pool_ptr(g, b, d.c0_pool)[d.c0_off + (int64_t)row * d.ldc0 + col]);
+          } else if (d.has_c0 == 2) {
+            // A_SS(row, col) = sum of the children's update blocks at the mapped position,
+            // summed in child order as the front assembly sums the other entries
+            double2 a = make_double2(0.0, 0.0);
+            for (int c = 0; c < d.nchild; ++c) {
+              const int ii = g.inv_maps[d.inv_off[c] + d.kid_base + row];
+              const int jj = g.inv_maps[d.inv_off[c] + d.kid_base + col];
+              if (ii >= 0 && jj >= 0) {
+                const int cp = d.child_p[c];
+                a = cadd(a, F[d.child_off[c] + (int64_t)(cp + ii) * d.child_ld[c] + cp + jj]);
+              }
+            }
+            v = cadd(v, a);
+          }
           pool_ptr(g, b, d.c_pool)[d.c_off + (int64_t)row * d.ldc + col] = v;
         } else if (MODE == 1) {
           W[d.rt_off + (int64_t)row * d.N + col] = acc;
@@ -368,8 +384,8 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
-                 int64_t rhs_stride) {
-  GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride, rhs, rhs_stride};
+                 int64_t rhs_stride, const int32_t* inv_maps) {
+  GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride, rhs, rhs_stride, inv_maps};
   const dim3 blk(kGemmThreads);
   if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
   else if (mode == 0 && tile == kTile128x64) hipLaunchKernelGGL((k_gemm<0, 4, 2, 16, 1>), grid, blk, 0, st, descs, ndesc, g);

@@ -201,8 +201,15 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       ss.a_pool = 0; ss.a_off = o + p * ld; ss.lda = (int)ld;
       ss.b_pool = 1; ss.b_off = o + p; ss.ldb = (int)ld;
       ss.c_pool = 1; ss.c_off = o + p * ld + p; ss.ldc = (int)ld;
-      ss.c0_pool = 0; ss.c0_off = o + p * ld + p; ss.ldc0 = (int)ld;
-      ss.alpha = -1.0; ss.has_c0 = 1;
+      ss.alpha = -1.0; ss.has_c0 = 2;  // A_SS straight from the children's update blocks
+      ss.nchild = fr.nchild; ss.kid_base = fr.p;
+      for (int c = 0; c < fr.nchild; ++c) {
+        const clsel::Front& ch = P.fronts[fr.child[c]];
+        ss.inv_off[c] = fr.inv_off[c];
+        ss.child_off[c] = ch.fbuf * pool + ch.off;
+        ss.child_p[c] = ch.p;
+        ss.child_ld[c] = ch.ld;
+      }
       ss.tiles_n = (int)cdiv64(ss.N, 64);
       ss.tile_start = ts; ts += cdiv64(ss.M, 64) * ss.tiles_n;
       gs.push_back(ss);
@@ -358,7 +365,19 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
           REQ(g.a_off + (int64_t)(g.M - 1) * g.lda + g.K <= lim(g.a_pool), "gemm A", g.a_off, lim(g.a_pool));
           REQ(g.b_off + (int64_t)(g.K - 1) * g.ldb + g.N <= lim(g.b_pool), "gemm B", g.b_off, lim(g.b_pool));
           REQ(g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N <= lim(g.c_pool), "gemm C", g.c_off, lim(g.c_pool));
-          if (g.has_c0) REQ(g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N <= lim(g.c0_pool), "gemm C0", g.c0_off, 0);
+          if (g.has_c0 == 1) REQ(g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N <= lim(g.c0_pool), "gemm C0", g.c0_off, 0);
+          REQ(g.has_c0 >= 0 && g.has_c0 <= 2, "gemm C0 kind", g.has_c0, 2);
+          if (g.has_c0 == 2) {
+            REQ(g.nchild >= 0 && g.nchild <= 4 && g.kid_base >= 0, "gemm children", g.nchild, 4);
+            for (int c = 0; c < g.nchild; ++c) {
+              const int64_t rows = (int64_t)g.kid_base + std::max(g.M, g.N);
+              REQ(g.inv_off[c] >= 0 && g.inv_off[c] + rows <= (int64_t)P.inv_maps.size(), "gemm child map", g.inv_off[c], 0);
+              int64_t cs = 0;
+              for (int64_t r = 0; r < rows; ++r) cs = std::max<int64_t>(cs, P.inv_maps[g.inv_off[c] + r] + 1);
+              REQ(cs == 0 || g.child_off[c] + (int64_t)(g.child_p[c] + cs - 1) * g.child_ld[c] + g.child_p[c] + cs <= two,
+                  "gemm child front", g.child_off[c], two);
+            }
+          }
         } else {
           const int H = g.N;  // both modes span every column of the front
           REQ(g.x_off + (int64_t)H * g.ld <= two && g.y_off + (int64_t)H * g.ld <= two, "gemm front", g.x_off, two);
@@ -698,7 +717,7 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
         }
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws,
-                           b->L.iws_elems, nullptr, 0);
+                           b->L.iws_elems, nullptr, 0, b->d_inv);
         if (timed) HIPCHK(hipEventRecord(e1, b->st));
         break;
       }
@@ -1143,7 +1162,7 @@ int enqueue_solve(cl_batch b, const void* rhs_dev, void* x_dev) {
       default:
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
-                           b->rhs, stride);
+                           b->rhs, stride, b->d_inv);
     }
     HIPCHK(hipGetLastError());
     return 0;
