@@ -79,7 +79,7 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
 }
 
 template <int MODE, int TM, int TN, int BK, int NBUF>
-__global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : (MODE < 2 ? 4 : 2))
+__global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : 4)
 k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
   constexpr int RA = BM * BK / kGemmThreads, RB = BN * BK / kGemmThreads;  // loads per thread per stage
@@ -186,26 +186,6 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       scol[t] = (sub % vc) * 16;
     }
   }
-
-  // mode 2: the old front values that the update is subtracted from, loaded during the
-  // last K stage so the loads overlap its MFMAs
-  double2 base[TM][TN][4];
-  auto load_base = [&]() __attribute__((always_inline)) {
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + wm * (BM / 2) + i * 16 + 4 * r + l4;
-        const bool rok = row < d.M && !(row >= d.k && row < d.k + d.nbk);
-        const double2* xr = rok ? F + d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld : nullptr;
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-          const int col = col0 + wn * (BN / 2) + j * 16 + l16;
-          const bool ok = rok && col < d.N && !(col >= d.k && col < d.k + d.nbk);
-          base[i][j][r] = ok ? xr[col] : make_double2(0.0, 0.0);
-        }
-      }
-  };
 
   auto load_stage = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
@@ -315,7 +295,6 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       store_stage(0);
       __syncthreads();
       // mode 2 fetches its subtrahend during the last stage so the loads overlap the MFMAs
-      if (MODE == 2) load_base();
       mfma_stage(0, edge);
     } else {
       // two buffers: stage st+1 goes into the idle buffer after stage st's MFMAs (that
@@ -329,7 +308,6 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
         if (st + 2 < nst) load_stage((st + 2) * BK);
         __syncthreads();
       }
-      if (MODE == 2) load_base();
       mfma_stage((nst - 1) & 1, edge);
     }
   };
@@ -340,7 +318,23 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   else pipeline(std::true_type{});
 
 #pragma unroll
-  for (int i = 0; i < TM; ++i)
+  for (int i = 0; i < TM; ++i) {
+    // mode 2: the subtrahend of this row block of sub-tiles, all loads in flight together
+    double2 bs[TN][4];
+    if constexpr (MODE == 2) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + wm * (BM / 2) + i * 16 + 4 * r + l4;
+        const bool rok = row < d.M && !(row >= d.k && row < d.k + d.nbk);
+        const double2* xr = rok ? F + d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld : nullptr;
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+          const int col = col0 + wn * (BN / 2) + j * 16 + l16;
+          const bool ok = rok && col < d.N && !(col >= d.k && col < d.k + d.nbk);
+          bs[j][r] = ok ? xr[col] : make_double2(0.0, 0.0);
+        }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j)
 #pragma unroll
@@ -376,9 +370,10 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
           // Y = base - A*Rt, base = X[rmap(row)][col] off the pivot rows and panel columns
           int oc = col;
           if (d.last && col < d.p) oc = IW[d.rowid_off + col];
-          F[d.y_off + (int64_t)row * d.ld + oc] = csub(base[i][j][r], acc);
+          F[d.y_off + (int64_t)row * d.ld + oc] = csub(bs[j][r], acc);
         }
       }
+  }
 }
 
 void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
