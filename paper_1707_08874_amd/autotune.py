@@ -94,9 +94,10 @@ def autotune(dims, batch, grid=None, reps=3, path: str | None = None, verbose=Tr
     good = [r for r in results if r.get("ok", True)]
     fastest = min(r["seconds"] for r in good)
     # among the candidates within 1% of the fastest, keep the one closest to the default
-    # plan's result (the options change rounding, and some choices round worse)
+    # plan's result (the options change rounding, and some choices round worse); on a tie
+    # an explicit set of options beats the empty default set, so the record names them
     near = [r for r in good if r["seconds"] <= 1.01 * fastest]
-    best = min(near, key=lambda r: (r.get("max_dev_from_default", 0.0), r["seconds"]))
+    best = min(near, key=lambda r: (r.get("max_dev_from_default", 0.0), not r["options"], r["seconds"]))
     path = path or os.environ.get("CLSEL_TUNE_CACHE", DEFAULT_CACHE)
     cache = load(path)
     cache[key(dims, batch)] = {"options": best["options"], "seconds": best["seconds"],
