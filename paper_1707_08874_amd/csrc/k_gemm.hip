@@ -1,7 +1,8 @@
 // Complex128 GEMM on the FP64 matrix cores (v_mfma_f64_16x16x4_f64).
 //
 // A complex product C = A*B is four real products: Re C = Ar*Br - Ai*Bi,
-// Im C = Ar*Bi + Ai*Br (no 3M trick, so rounding matches the plain 4-multiply form).
+// Im C = Ar*Bi + Ai*Br (not Gauss's three products, whose imaginary part, a difference
+// of larger sums, rounds worse).
 // Each work-group computes a BM x BN complex tile (64 x 64, or 128 x 64 / 128 x 128)
 // with 4 waves (2 x 2), each wave a (BM/2) x (BN/2) tile made of TM x TN MFMA tiles of
 // 16 x 16 with two FP64 accumulators (real part fed by Ar*Br and (-Ai)*Bi, imaginary
@@ -294,7 +295,6 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       }
       store_stage(0);
       __syncthreads();
-      // mode 2 fetches its subtrahend during the last stage so the loads overlap the MFMAs
       mfma_stage(0, edge);
     } else {
       // two buffers: stage st+1 goes into the idle buffer after stage st's MFMAs (that
