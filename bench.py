@@ -64,6 +64,9 @@ def main():
     ap.add_argument("--library-gemm", action="store_true",
                     help="each mode-0 GEMM launch of the batched step (kernel time from HIP events) "
                          "beside the library's batched complex128 GEMM (torch.bmm) on the same problems")
+    ap.add_argument("--parity-sweep", type=int, default=0, metavar="K",
+                    help="run the batched step once and check its first K configurations against "
+                         "the CPU oracle, one line per configuration")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     args = ap.parse_args()
@@ -86,6 +89,8 @@ def main():
         return stochastic(args)
     if args.library_gemm:
         return library_gemm(args)
+    if args.parity_sweep:
+        return parity_sweep(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -343,6 +348,67 @@ def library_gemm(args):
     print(json.dumps({"launch": "library reference", "problems": {"4096x4096x4096": 4}, "gflop": fl / 1e9,
                       "library_ms": ms, "library_tflops": fl / ms / 1e9}), flush=True)
     return 0
+
+
+def parity_sweep(args):
+    """Oracle parity of the first K configurations of the batched workload (same plan
+    and launch configuration as the timed step)."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_1707_08874_amd import autotune, clsel
+    from paper_1707_08874_amd.inputs import gen_batch, eps_for_seed
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import TOL, block_errors, drift_errors, kappa1, tolerance
+
+    dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
+    K = min(args.parity_sweep, B)
+    opts = autotune.options(dims, B)
+    if args.nb:
+        opts["nb"] = args.nb
+    if args.leaf:
+        opts["leaf_sites"] = args.leaf
+    plan = clsel.Plan(dims, **opts)
+    V = plan.info()["volume"]
+    links = gen_batch(dims, range(B))
+    lt = torch.from_numpy(links).to("cuda")
+    sel = torch.empty((B, V, 9, 3, 3), dtype=torch.complex128, device="cuda")
+    drift = torch.empty((B, V, 4, 8), dtype=torch.complex128, device="cuda")
+    batch = clsel.Batch(plan, B)
+    batch.run(lt, m, mu, sel, drift)
+    batch.sync()
+    status = batch.status()
+    sel, drift = sel[:K].cpu().numpy(), drift[:K].cpu().numpy()
+    batch.close()
+    print(f"[sweep] batched step done (B={B}, plan {opts}); checking {K} configurations",
+          file=sys.stderr, flush=True)
+    rows = []
+    for c in range(K):
+        D = oracle.dirac_dense(links[c], dims, m, mu)
+        Z = oracle.inverse_dense(D)
+        ref_sel = oracle.selected_blocks(Z, dims)
+        ref_drift = oracle.drift_from_blocks(ref_sel, links[c], dims, mu)
+        kap = kappa1(D, Z)
+        del D, Z
+        be = block_errors(sel[c], ref_sel)
+        de = drift_errors(drift[c], ref_drift)
+        r = {"config": c, "eps": eps_for_seed(c), "kappa1_D": kap,
+             "worst_block_rel_err": float(be.max()), "median_block_rel_err": float(np.median(be)),
+             "blocks_above_1e-10": int((be > TOL).sum()),
+             "worst_drift_rel_err_per_link": float(de.max()),
+             "links_above_1e-10": int((de > TOL).sum()),
+             "pass_1e-10": bool(be.max() <= TOL and de.max() <= TOL),
+             "pass_kappa_gate": bool(be.max() <= tolerance(kap) and de.max() <= tolerance(kap)),
+             "status": int(status[c])}
+        rows.append(r)
+        print(f"[sweep] config {c}: eps {r['eps']:.3f} kappa_1 {kap:.3g} worst block "
+              f"{r['worst_block_rel_err']:.2e} ({r['blocks_above_1e-10']} of {be.size} above 1e-10) "
+              f"worst link drift {r['worst_drift_rel_err_per_link']:.2e} "
+              f"({r['links_above_1e-10']} of {de.size} above 1e-10)", file=sys.stderr, flush=True)
+    print(json.dumps({"parity_sweep": rows, "plan": opts, "batch": B, "dims": list(dims),
+                      "pass_1e-10": sum(r["pass_1e-10"] for r in rows),
+                      "pass_kappa_gate": sum(r["pass_kappa_gate"] for r in rows), "checked": K}))
 
 
 def stochastic(args):
