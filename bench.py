@@ -69,6 +69,7 @@ def main():
                          "the CPU oracle, one line per configuration")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
+    ap.add_argument("--max-pivot-rows", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the workload is per-GPU batched selected "
@@ -110,6 +111,8 @@ def main():
             o["nb"] = args.nb
         if args.leaf:
             o["leaf_sites"] = args.leaf
+        if args.max_pivot_rows:
+            o["max_pivot_rows"] = args.max_pivot_rows
         return o
 
     opts_b = plan_opts(B)
@@ -369,6 +372,8 @@ def parity_sweep(args):
         opts["nb"] = args.nb
     if args.leaf:
         opts["leaf_sites"] = args.leaf
+    if args.max_pivot_rows:
+        opts["max_pivot_rows"] = args.max_pivot_rows
     plan = clsel.Plan(dims, **opts)
     V = plan.info()["volume"]
     links = gen_batch(dims, range(B))

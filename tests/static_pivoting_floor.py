@@ -92,7 +92,8 @@ def main():
     ap.add_argument("--m", type=float, default=0.05)
     ap.add_argument("--mu", type=float, default=0.25)
     ap.add_argument("--leaf", type=int, default=4, help="sites per nested-dissection leaf")
-    ap.add_argument("--max-pivot-rows", type=int, default=1536)
+    ap.add_argument("--max-pivot-rows", type=int, default=0,
+                    help="separators with more rows become a chain of supernodes (0: library default)")
     ap.add_argument("--check-worst", type=int, default=3,
                     help="worst blocks re-checked against iteratively refined columns")
     a = ap.parse_args()
