@@ -183,7 +183,7 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
         sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from parity import block_errors, drift_errors, kappa1, tolerance
+        from parity import block_errors, drift_errors, kappa1, normwise_error, tolerance
         t = time.perf_counter()
         D = oracle.dirac_dense(links[0], dims, m, mu)
         Z = oracle.inverse_dense(D)
@@ -199,6 +199,7 @@ def main():
         be = block_errors(sel0, ref_sel)
         parity = {"config": 0, "worst_block_rel_err": float(be.max()),
                   "blocks_above_1e-10": int((be > 1e-10).sum()), "blocks": int(be.size),
+                  "worst_block_err_vs_largest_block": normwise_error(sel0, ref_sel),
                   "worst_drift_rel_err_per_link": float(drift_errors(drift0, ref_drift).max()),
                   "kappa1_D": kap, "tolerance": tolerance(kap),
                   "pass": bool(be.max() <= tolerance(kap)
@@ -363,7 +364,7 @@ def parity_sweep(args):
     from paper_1707_08874_amd import autotune, clsel
     from paper_1707_08874_amd.inputs import gen_batch, eps_for_seed
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    from parity import TOL, block_errors, drift_errors, kappa1, tolerance
+    from parity import TOL, block_errors, drift_errors, kappa1, normwise_error, tolerance
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     K = min(args.parity_sweep, B)
@@ -401,6 +402,7 @@ def parity_sweep(args):
         r = {"config": c, "eps": eps_for_seed(c), "kappa1_D": kap,
              "worst_block_rel_err": float(be.max()), "median_block_rel_err": float(np.median(be)),
              "blocks_above_1e-10": int((be > TOL).sum()),
+             "worst_block_err_vs_largest_block": normwise_error(sel[c], ref_sel),
              "worst_drift_rel_err_per_link": float(de.max()),
              "links_above_1e-10": int((de > TOL).sum()),
              "pass_1e-10": bool(be.max() <= TOL and de.max() <= TOL),
@@ -409,6 +411,7 @@ def parity_sweep(args):
         rows.append(r)
         print(f"[sweep] config {c}: eps {r['eps']:.3f} kappa_1 {kap:.3g} worst block "
               f"{r['worst_block_rel_err']:.2e} ({r['blocks_above_1e-10']} of {be.size} above 1e-10) "
+              f"normwise {r['worst_block_err_vs_largest_block']:.1e} "
               f"worst link drift {r['worst_drift_rel_err_per_link']:.2e} "
               f"({r['links_above_1e-10']} of {de.size} above 1e-10)", file=sys.stderr, flush=True)
     print(json.dumps({"parity_sweep": rows, "plan": opts, "batch": B, "dims": list(dims),

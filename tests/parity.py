@@ -36,6 +36,14 @@ def block_errors(got, ref):
     return np.linalg.norm(g - r, axis=1) / np.maximum(np.linalg.norm(r, axis=1), 1e-300)
 
 
+def normwise_error(got, ref):
+    """Largest block error relative to the largest reference block (reported, not gated):
+    it separates errors that are large in absolute terms from those of small blocks."""
+    g = np.asarray(got).reshape(-1, 9)
+    r = np.asarray(ref).reshape(-1, 9)
+    return float(np.linalg.norm(g - r, axis=1).max() / max(np.linalg.norm(r, axis=1).max(), 1e-300))
+
+
 def drift_errors(got, ref):
     g = np.asarray(got).reshape(-1, 8)
     r = np.asarray(ref).reshape(-1, 8)
