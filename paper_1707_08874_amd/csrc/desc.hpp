@@ -57,6 +57,9 @@ struct GemmDesc {
   int lda, ldb, ldc, ldc0;
   double alpha;
   int has_c0;             // 0: none; 1: C0 at c0_off; 2: the children's update blocks (below)
+  // 1: sum K in chunks of kKChunk, the running sum kept in C between chunks (C must not
+  // alias A, B or C0); 0: one chain of products over all of K
+  int kblock;
   // has_c0 = 2 (Schur complement S = A_SS - A_SJ U^): A_SS is the sum over the children
   // of their update blocks at the mapped positions, read here instead of from an
   // assembled copy. Output (row, col) is front entry (kid_base + row, kid_base + col).

@@ -282,6 +282,45 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   };
 
   const int nst = (d.K + BK - 1) / BK;
+  // Blocked summation (mode 0, d.kblock): the accumulators hold the sum over one chunk of
+  // kKChunk products; at the end of each chunk but the last, it is added to the running
+  // total, which waits in C (each lane reads and writes only its own outputs), and the
+  // accumulators restart from zero. A single chain over all of K would add every product
+  // to an ever larger partial sum; with chunks the rounding grows with the chunk length
+  // plus the number of chunks instead, which matters where the result is much smaller
+  // than the products (the selected-inversion and Schur-complement updates).
+  constexpr int kStagesPerChunk = kKChunk / BK;
+  static_assert(kKChunk % BK == 0, "chunk of whole stages");
+  // (the 128 x 128 tile keeps one chain: its accumulators leave no registers for the
+  // partial sums, which would spill)
+  constexpr bool kChunkable = MODE == 0 && TM * TN <= 8;
+  const bool chunked = kChunkable && d.kblock && nst > kStagesPerChunk;
+  auto flush_chunk = [&](bool first) __attribute__((always_inline)) {
+    // the lane coordinates pass through an empty asm, so that the output addresses are
+    // formed here and not kept in registers through the whole K loop
+    int lr = l4, lc = l16;
+    asm volatile("" : "+v"(lr), "+v"(lc));
+    double2* C = pool_ptr(g, b, d.c_pool) + d.c_off;
+#pragma unroll
+    for (int t = 0; t < kSlots; ++t) {
+      const int i = t / TN, j = t % TN;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = row0 + srow[t] + 4 * r + lr;
+        const int col = col0 + scol[t] + lc;
+        if (sok[t] && row < d.M && col < d.N) {
+          double2* pc = C + (int64_t)row * d.ldc + col;
+          double2 v = make_double2(cr[i][j][r], ci[i][j][r]);
+          if (!first) v = cadd(v, *pc);
+          *pc = v;
+        }
+      }
+      cr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      ci[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      // one slot's four loads in flight at a time: the accumulators fill the registers
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
   auto pipeline = [&](auto edge) __attribute__((always_inline)) {
     load_stage(0);
     if (NBUF == 1) {
@@ -291,6 +330,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
         __syncthreads();
         load_stage((st + 1) * BK);
         mfma_stage(0, edge);
+        if constexpr (kChunkable) {
+          if (chunked && (st + 1) % kStagesPerChunk == 0) flush_chunk(st + 1 == kStagesPerChunk);
+        }
         __syncthreads();
       }
       store_stage(0);
@@ -305,6 +347,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       for (int st = 0; st + 1 < nst; ++st) {
         mfma_stage(st & 1, edge);
         store_stage((st + 1) & 1);
+        if constexpr (kChunkable) {
+          if (chunked && (st + 1) % kStagesPerChunk == 0) flush_chunk(st + 1 == kStagesPerChunk);
+        }
         if (st + 2 < nst) load_stage((st + 2) * BK);
         __syncthreads();
       }
@@ -344,8 +389,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
         const int row = row0 + (MODE == 1 ? wm * (BM / 2) + i * 16 : srow[t]) + 4 * r + l4;
         const int col = col0 + (MODE == 1 ? wn * (BN / 2) + j * 16 : scol[t]) + l16;
         if ((MODE != 1 && !sok[t]) || row >= d.M || col >= d.N) continue;
-        const double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
+        double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
         if (MODE == 0) {
+          if (chunked) acc = cadd(acc, pool_ptr(g, b, d.c_pool)[d.c_off + (int64_t)row * d.ldc + col]);
           double2 v = cscale(acc, d.alpha);
           if (d.has_c0 == 1) {
             v = cadd(v, pool_ptr(g, b, d.c0_pool)[d.c0_off + (int64_t)row * d.ldc0 + col]);

@@ -13,6 +13,9 @@ constexpr int kMaxNB = 64;            // widest Gauss-Jordan block
 // output tiles of the plain (mode 0) GEMMs
 constexpr int kTile64 = 64, kTile128x64 = 12864, kTile128 = 128;
 constexpr int kMaxPivotRows = 1536;   // pivot rows per supernode the panel kernel can hold
+// K-chunk of the blocked summation of the plain GEMMs: each output sums kKChunk products
+// in the matrix-core accumulator, then adds that partial sum to its running total
+constexpr int kKChunk = 128;
 // front assembly and Z_SS gather: tile of one 256-thread work-group (one column per thread)
 constexpr int kAsmTileRows = 8, kAsmTileCols = 256;
 constexpr int32_t kStatusSingular = -4;

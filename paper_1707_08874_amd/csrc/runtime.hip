@@ -202,6 +202,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       ss.b_pool = 1; ss.b_off = o + p; ss.ldb = (int)ld;
       ss.c_pool = 1; ss.c_off = o + p * ld + p; ss.ldc = (int)ld;
       ss.alpha = -1.0; ss.has_c0 = 2;  // A_SS straight from the children's update blocks
+      ss.kblock = 1;
       ss.nchild = fr.nchild; ss.kid_base = fr.p;
       for (int c = 0; c < fr.nchild; ++c) {
         const clsel::Front& ch = P.fronts[fr.child[c]];
@@ -218,7 +219,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       sj.a_pool = 0; sj.a_off = o + p * ld; sj.lda = (int)ld;
       sj.b_pool = 1; sj.b_off = o; sj.ldb = (int)ld;
       sj.c_pool = 1; sj.c_off = o + p * ld; sj.ldc = (int)ld;
-      sj.alpha = -1.0; sj.has_c0 = 0;
+      sj.alpha = -1.0; sj.has_c0 = 0; sj.kblock = 1;
       sj.tiles_n = (int)cdiv64(sj.N, 64);
       sj.tile_start = ts; ts += cdiv64(sj.M, 64) * sj.tiles_n;
       gs.push_back(sj);
@@ -251,7 +252,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       sj.a_pool = zp; sj.a_off = o + p * ld + p; sj.lda = ld;
       sj.b_pool = fp; sj.b_off = o + p * ld; sj.ldb = ld;
       sj.c_pool = zp; sj.c_off = o + p * ld; sj.ldc = ld;
-      sj.alpha = 1.0; sj.has_c0 = 0;
+      sj.alpha = 1.0; sj.has_c0 = 0; sj.kblock = 1;
       sj.tiles_n = (int)cdiv64(sj.N, 64);
       sj.tile_start = ta; ta += cdiv64(sj.M, 64) * sj.tiles_n;
       ga.push_back(sj);
@@ -261,7 +262,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       js.a_pool = fp; js.a_off = o + p; js.lda = ld;
       js.b_pool = zp; js.b_off = o + p * ld + p; js.ldb = ld;
       js.c_pool = zp; js.c_off = o + p; js.ldc = ld;
-      js.alpha = -1.0; js.has_c0 = 0;
+      js.alpha = -1.0; js.has_c0 = 0; js.kblock = 1;
       js.tiles_n = (int)cdiv64(js.N, 64);
       js.tile_start = ta; ta += cdiv64(js.M, 64) * js.tiles_n;
       ga.push_back(js);
@@ -272,7 +273,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       jj.b_pool = zp; jj.b_off = o + p * ld; jj.ldb = ld;
       jj.c_pool = zp; jj.c_off = o; jj.ldc = ld;
       jj.c0_pool = fp; jj.c0_off = o; jj.ldc0 = ld;
-      jj.alpha = -1.0; jj.has_c0 = 1;
+      jj.alpha = -1.0; jj.has_c0 = 1; jj.kblock = 1;
       jj.tiles_n = (int)cdiv64(jj.N, 64);
       jj.tile_start = tb; tb += cdiv64(jj.M, 64) * jj.tiles_n;
       gb.push_back(jj);
@@ -367,6 +368,26 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
           REQ(g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N <= lim(g.c_pool), "gemm C", g.c_off, lim(g.c_pool));
           if (g.has_c0 == 1) REQ(g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N <= lim(g.c0_pool), "gemm C0", g.c0_off, 0);
           REQ(g.has_c0 >= 0 && g.has_c0 <= 2, "gemm C0 kind", g.has_c0, 2);
+          if (g.kblock) {
+            // the running sum waits in C between K chunks: C may not share an element
+            // with A, B or C0 (blocks of one front share its ld; other fronts lie apart)
+            auto apart = [&](int pool_x, int64_t off_x, int64_t rows, int64_t cols, int64_t ld) {
+              if (pool_x != g.c_pool) return true;
+              const int64_t c_end = g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N;
+              const int64_t x_end = off_x + (rows - 1) * ld + cols;
+              if (x_end <= g.c_off || c_end <= off_x) return true;
+              if (ld != g.ldc) return false;
+              const int64_t delta = off_x - g.c_off;
+              const int64_t r = delta >= 0 ? delta / ld : -((-delta + ld - 1) / ld);
+              const int64_t c = delta - r * ld;
+              if (c + cols > ld) return false;
+              return r + rows <= 0 || r >= g.M || c + cols <= 0 || c >= g.N;
+            };
+            REQ(apart(g.a_pool, g.a_off, g.M, g.K, g.lda), "gemm chunked C overlaps A", g.c_off, g.a_off);
+            REQ(apart(g.b_pool, g.b_off, g.K, g.N, g.ldb), "gemm chunked C overlaps B", g.c_off, g.b_off);
+            if (g.has_c0 == 1)
+              REQ(apart(g.c0_pool, g.c0_off, g.M, g.N, g.ldc0), "gemm chunked C overlaps C0", g.c_off, g.c0_off);
+          }
           if (g.has_c0 == 2) {
             REQ(g.nchild >= 0 && g.nchild <= 4 && g.kid_base >= 0, "gemm children", g.nchild, 4);
             for (int c = 0; c < g.nchild; ++c) {
