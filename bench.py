@@ -169,6 +169,7 @@ def main():
             pb.sync()
             lat.append(time.perf_counter() - a)
         lat = np.array(lat)
+        plain_sel0, plain_drift0 = s1[0].cpu().numpy(), d1[0].cpu().numpy()
         plain = {"value": 1.0 / lat.mean(), "unit": "configs/s",
                  "p50_ms": float(np.median(lat) * 1e3),
                  "p99_ms": float(np.quantile(lat, 0.99) * 1e3), "reps": args.plain_reps,
@@ -204,6 +205,9 @@ def main():
                   "kappa1_D": kap, "tolerance": tolerance(kap),
                   "pass": bool(be.max() <= tolerance(kap)
                                and drift_errors(drift0, ref_drift).max() <= tolerance(kap))}
+        if plain is not None:
+            parity["plain_worst_block_rel_err"] = float(block_errors(plain_sel0, ref_sel).max())
+            parity["plain_worst_drift_rel_err_per_link"] = float(drift_errors(plain_drift0, ref_drift).max())
 
     avg_launch_ms = gemm_ms / max(launches, 1)
     achieved = gemm_flops / max(gemm_ms, 1e-9) / 1e9  # TFLOP/s
