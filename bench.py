@@ -391,6 +391,18 @@ def parity_sweep(args):
     status = batch.status()
     sel, drift = sel[:K].cpu().numpy(), drift[:K].cpu().numpy()
     batch.close()
+    # the plain single-configuration plan (graph replay), on the same configurations
+    opts1 = autotune.options(dims, 1)
+    pb = clsel.Batch(clsel.Plan(dims, **opts1), 1)
+    pb.use_graph(True)
+    sel1, drift1, status1 = [], [], []
+    for c in range(K):
+        s1, d1 = pb.run(lt[c:c + 1].contiguous(), m, mu)
+        pb.sync()
+        status1.append(int(pb.status()[0]))
+        sel1.append(s1[0].cpu().numpy())
+        drift1.append(d1[0].cpu().numpy())
+    pb.close()
     print(f"[sweep] batched step done (B={B}, plan {opts}); checking {K} configurations",
           file=sys.stderr, flush=True)
     rows = []
@@ -411,14 +423,21 @@ def parity_sweep(args):
              "links_above_1e-10": int((de > TOL).sum()),
              "pass_1e-10": bool(be.max() <= TOL and de.max() <= TOL),
              "pass_kappa_gate": bool(be.max() <= tolerance(kap) and de.max() <= tolerance(kap)),
-             "status": int(status[c])}
+             "status": int(status[c]),
+             "plain_worst_block_rel_err": float(block_errors(sel1[c], ref_sel).max()),
+             "plain_worst_drift_rel_err_per_link": float(drift_errors(drift1[c], ref_drift).max()),
+             "plain_status": status1[c]}
+        r["plain_pass_kappa_gate"] = bool(r["plain_worst_block_rel_err"] <= tolerance(kap)
+                                          and r["plain_worst_drift_rel_err_per_link"] <= tolerance(kap))
         rows.append(r)
         print(f"[sweep] config {c}: eps {r['eps']:.3f} kappa_1 {kap:.3g} worst block "
               f"{r['worst_block_rel_err']:.2e} ({r['blocks_above_1e-10']} of {be.size} above 1e-10) "
               f"normwise {r['worst_block_err_vs_largest_block']:.1e} "
               f"worst link drift {r['worst_drift_rel_err_per_link']:.2e} "
-              f"({r['links_above_1e-10']} of {de.size} above 1e-10)", file=sys.stderr, flush=True)
-    print(json.dumps({"parity_sweep": rows, "plan": opts, "batch": B, "dims": list(dims),
+              f"({r['links_above_1e-10']} of {de.size} above 1e-10); plain path worst block "
+              f"{r['plain_worst_block_rel_err']:.2e}", file=sys.stderr, flush=True)
+    print(json.dumps({"parity_sweep": rows, "plan": opts, "plan_plain": opts1, "batch": B, "dims": list(dims),
+                      "plain_pass_kappa_gate": sum(r["plain_pass_kappa_gate"] for r in rows),
                       "pass_1e-10": sum(r["pass_1e-10"] for r in rows),
                       "pass_kappa_gate": sum(r["pass_kappa_gate"] for r in rows), "checked": K}))
 

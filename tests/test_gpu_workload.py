@@ -78,7 +78,8 @@ def workload():
         print(f"[gpu] config {c}: worst block {r['worst']:.2e} median {r['median']:.1e} "
               f"normwise {r['normwise']:.1e} worst link {r['drift_worst']:.2e} "
               f"scaled gate {tol:.1e}", flush=True)
-    return dict(status=status, status1=status1, rows=rows)
+    return dict(status=status, status1=status1, rows=rows, same_plan=opts1 == opts,
+                plain_equal=bool(np.array_equal(sel_p[0], sel_b[0]) and np.array_equal(drift_p[0], drift_b[0])))
 
 
 def test_status(workload):
@@ -102,6 +103,12 @@ def test_plain_path_sample(workload):
     print(f"[gpu] plain path, config 0: worst block {r['plain_worst']:.2e}, "
           f"worst link {r['plain_drift_worst']:.2e}", flush=True)
     assert r["plain_worst"] <= r["tol"] and r["plain_drift_worst"] <= r["tol"], r
+
+
+def test_plain_equals_batched_with_the_same_plan(workload):
+    if not workload["same_plan"]:
+        pytest.skip("the plain and batched plans differ")
+    assert workload["plain_equal"]
 
 
 def test_scaled_gate_every_configuration(workload):
