@@ -11,7 +11,10 @@
 // stage's global loads go to registers one stage ahead; with two LDS buffers (the
 // 64 x 64 tile, BK = 8) the registers are stored into the idle buffer right after the
 // current stage's MFMAs, so there is one barrier per stage and the kernel fits four
-// waves per SIMD. The accumulation order over k is the same for every BK.
+// waves per SIMD. In mode 0 (where the launch allows it) each output is summed in chunks
+// of kKChunk products whose partial sums are added to a running total kept in C; the
+// accumulation order over k is then the same for the 64 x 64 and 128 x 64 tiles, while
+// the 128 x 128 tile sums all of K in one chain.
 //
 // MFMA 16x16x4 f64 lane layout (measured on gfx950): A operand lane l holds
 // A[l%16][l/16], B operand lane l holds B[l/16][l%16], accumulator element r of
