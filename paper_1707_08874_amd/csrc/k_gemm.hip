@@ -12,9 +12,9 @@
 // 64 x 64 tile, BK = 8) the registers are stored into the idle buffer right after the
 // current stage's MFMAs, so there is one barrier per stage and the kernel fits four
 // waves per SIMD. In mode 0 (where the launch allows it) each output is summed in chunks
-// of kKChunk products whose partial sums are added to a running total kept in C; the
-// accumulation order over k is then the same for the 64 x 64 and 128 x 64 tiles, while
-// the 128 x 128 tile sums all of K in one chain.
+// of kKChunk products (longer where K exceeds kMaxChunks of them) whose partial sums are
+// added to a running total kept in C; the accumulation order over k is then the same for
+// the 64 x 64 and 128 x 64 tiles, while the 128 x 128 tile sums all of K in one chain.
 //
 // MFMA 16x16x4 f64 lane layout (measured on gfx950): A operand lane l holds
 // A[l%16][l/16], B operand lane l holds B[l/16][l%16], accumulator element r of
@@ -297,7 +297,10 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   // (the 128 x 128 tile keeps one chain: its accumulators leave no registers for the
   // partial sums, which would spill)
   constexpr bool kChunkable = MODE == 0 && TM * TN <= 8;
-  const bool chunked = kChunkable && d.kblock && nst > kStagesPerChunk;
+  // at most kMaxChunks chunks: a longer K gets longer chunks, which bounds the round trips
+  // of the running totals (for K <= kMaxChunks * kKChunk the chunk is kKChunk)
+  const int chunk_stages = max(kStagesPerChunk, (nst + kMaxChunks - 1) / kMaxChunks);
+  const bool chunked = kChunkable && d.kblock && nst > chunk_stages;
   auto flush_chunk = [&](bool first) __attribute__((always_inline)) {
     // the lane coordinates pass through an empty asm, so that the output addresses are
     // formed here and not kept in registers through the whole K loop
@@ -328,13 +331,17 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     load_stage(0);
     if (NBUF == 1) {
       // one buffer: store the prefetched stage, prefetch the next, MFMAs, two barriers
+      int left = chunk_stages;
       for (int st = 0; st + 1 < nst; ++st) {
         store_stage(0);
         __syncthreads();
         load_stage((st + 1) * BK);
         mfma_stage(0, edge);
         if constexpr (kChunkable) {
-          if (chunked && (st + 1) % kStagesPerChunk == 0) flush_chunk(st + 1 == kStagesPerChunk);
+          if (chunked && --left == 0) {
+            flush_chunk(st + 1 == chunk_stages);
+            left = chunk_stages;
+          }
         }
         __syncthreads();
       }
@@ -347,11 +354,15 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       store_stage(0);
       __syncthreads();
       if (nst > 1) load_stage(BK);
+      int left = chunk_stages;
       for (int st = 0; st + 1 < nst; ++st) {
         mfma_stage(st & 1, edge);
         store_stage((st + 1) & 1);
         if constexpr (kChunkable) {
-          if (chunked && (st + 1) % kStagesPerChunk == 0) flush_chunk(st + 1 == kStagesPerChunk);
+          if (chunked && --left == 0) {
+            flush_chunk(st + 1 == chunk_stages);
+            left = chunk_stages;
+          }
         }
         if (st + 2 < nst) load_stage((st + 2) * BK);
         __syncthreads();
