@@ -64,6 +64,8 @@ def _oracle(links, dims, m, mu):
     ((4, 4, 4, 4), dict(nb=1)),                          # one pivot per step
     ((6, 4, 4, 6), dict(nb=32)),                         # non-cubic, several steps per front
     ((4, 6, 8, 4), dict(leaf_sites=12, nb=24)),          # larger leaves, odd tile edges
+    ((6, 4, 4, 6), dict(nb=32, gemm_tile=12864)),        # 128 x 64 tiles: one LDS buffer, chunked sums
+    ((4, 6, 8, 4), dict(gemm_tile=128)),                 # 128 x 128 tiles: one accumulation chain
 ])
 def test_single_config_matches_oracle(torch_cuda, dims, kw):
     U = gen_links(dims, 0, 0.1)
