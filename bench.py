@@ -4,11 +4,15 @@ One step = the whole hot path (assembly, supernodal factorisation, selected
 inversion, gather of the selected blocks, drift) over one batch of 64 synthetic
 8^3x4 configurations (seeds 0..63, eps ~ U[0.02, 0.3], m = 0.05, mu = 0.25) that
 share one symbolic analysis. Inputs are resident in HBM before the timed region.
-Also reported: the plain single-configuration path (graph replay, B = 1) with its
-p50/p99 latency, the roofline of the dominant kernel, the mode-0 complex GEMM
-(Schur complements and selected-inversion products: HIP events around each of its
-launches, algorithmic 8*M*N*K flops), parity of a sampled configuration against the
-CPU oracle, and the oracle itself timed on the host as the CPU baseline.
+The timed steps replay the whole step from one HIP graph with nothing else on the
+stream; `value` is their throughput. The same number of steps is then run eagerly
+with every mode-0 complex GEMM launch (Schur complements and selected-inversion
+products) between two HIP events on the batch stream: that pass gives the roofline
+of the dominant kernel (algorithmic 8*M*N*K flops over its measured launch time)
+and its own wall time (eager_ms_per_step). Also reported: the plain
+single-configuration path (graph replay, B = 1) with its p50/p99 latency, parity of
+a fixed sample of configurations against the CPU oracle at 1e-10 (every block and
+every drift component), and the oracle itself timed on the host as the CPU baseline.
 
     python bench.py [--steps K] [--warmup W] [--batch B] [--gpus 1]
 
@@ -30,6 +34,8 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
 COPY_BYTES = 1 << 30
 GEMM_KERNEL = "k_gemm<0, 2, 2, 8, 2>"
+# configurations of the batched workload checked against the oracle in every bench run
+PARITY_SAMPLE = (0, 5, 12, 36, 39, 45, 51, 61)
 
 
 def _blas_threads():
@@ -41,10 +47,36 @@ def _blas_threads():
         return os.cpu_count()
 
 
+def _host():
+    """The host the CPU baseline runs on: usable cores, CPU model, BLAS library and the
+    thread variables of the environment."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = "unknown"
+    try:
+        from threadpoolctl import threadpool_info
+        libs = [i for i in threadpool_info() if i.get("user_api") == "blas"]
+        if libs:
+            blas = f"{libs[0].get('internal_api', '?')} {libs[0].get('version', '?')}"
+    except Exception:
+        pass
+    return {"nproc": len(os.sched_getaffinity(0)), "cpu_model": model, "blas": blas,
+            "blas_threads": _blas_threads(),
+            "env": {k: os.environ[k] for k in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+                    if k in os.environ}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--plain-reps", type=int, default=20)
@@ -124,13 +156,12 @@ def main():
     sel = torch.empty((B, V, 9, 3, 3), dtype=torch.complex128, device="cuda")
     drift = torch.empty((B, V, 4, 8), dtype=torch.complex128, device="cuda")
 
-    # ---- batched path (eager, GEMM launches bracketed by events)
+    # ---- batched path: the whole step replayed from one HIP graph, nothing else in the timed loop
     batch = clsel.Batch(plan, B)
-    for _ in range(args.warmup):
+    batch.use_graph(True)
+    for _ in range(max(args.warmup, 1)):  # the first call captures the graph
         batch.run(lt, m, mu, sel, drift)
-    torch.cuda.synchronize()
-    batch.profile(1)  # mode-0 GEMM launches only
-    batch.profile_read()
+    batch.sync()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -138,14 +169,32 @@ def main():
     batch.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    gemm_ms, gemm_flops, gemm_bytes, launches = batch.profile_read()
-    batch.profile(0)
     status = batch.status()
     dt = t1 - t0
     value = B * args.steps / dt
-    print(f"[bench] batched: {dt / args.steps * 1e3:.1f} ms/step, {value:.2f} configs/s", file=sys.stderr, flush=True)
-    sel0 = sel[0].cpu().numpy()
-    drift0 = drift[0].cpu().numpy()
+    print(f"[bench] batched (graph replay): {dt / args.steps * 1e3:.1f} ms/step, {value:.2f} configs/s",
+          file=sys.stderr, flush=True)
+    sel_keep = {c: sel[c].cpu().numpy() for c in PARITY_SAMPLE if c < B}
+    drift_keep = {c: drift[c].cpu().numpy() for c in PARITY_SAMPLE if c < B}
+    # ---- the same step eager, every mode-0 GEMM launch between two HIP events on the batch
+    # stream (the roofline of the dominant kernel); its own wall time is reported beside
+    batch.use_graph(False)
+    batch.run(lt, m, mu, sel, drift)
+    batch.sync()
+    batch.profile(1)  # mode-0 GEMM launches only
+    batch.profile_read()
+    torch.cuda.synchronize()
+    e0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run(lt, m, mu, sel, drift)
+    batch.sync()
+    torch.cuda.synchronize()
+    eager_dt = time.perf_counter() - e0
+    gemm_ms, gemm_flops, gemm_bytes, launches = batch.profile_read()
+    batch.profile(0)
+    eager_same = all(np.array_equal(sel[c].cpu().numpy(), sel_keep[c]) for c in sel_keep)
+    sel0 = sel_keep[0]
+    drift0 = drift_keep[0]
     del batch, sel, drift
     torch.cuda.empty_cache()
 
@@ -178,36 +227,57 @@ def main():
         pb.close()
         print(f"[bench] plain: p50 {plain['p50_ms']:.2f} ms", file=sys.stderr, flush=True)
 
-    # ---- CPU oracle on one sampled configuration: baseline timing + parity
+    # ---- CPU oracle: baseline timing on configuration 0, parity on a sample of configurations
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
         import oracle
         sys.path.insert(0, os.path.join(ROOT, "tests"))
-        from parity import block_errors, drift_errors, kappa1, normwise_error, tolerance
-        t = time.perf_counter()
-        D = oracle.dirac_dense(links[0], dims, m, mu)
-        Z = oracle.inverse_dense(D)
-        ref_sel = oracle.selected_blocks(Z, dims)
-        ref_drift = oracle.drift_from_blocks(ref_sel, links[0], dims, mu)
-        tc = time.perf_counter() - t
-        kap = kappa1(D, Z)
-        del D, Z
-        cpu = {"value": 1.0 / tc, "unit": "configs/s", "cores": _blas_threads(), "kind": "oracle",
+        from parity import (TOL, block_errors, drift_componentwise, drift_errors, kappa1,
+                            normwise_error)
+        rows = []
+        tc = None
+        for c in sorted(sel_keep):
+            t = time.perf_counter()
+            D = oracle.dirac_dense(links[c], dims, m, mu)
+            Z = oracle.inverse_dense(D)
+            ref_sel = oracle.selected_blocks(Z, dims)
+            ref_drift = oracle.drift_from_blocks(ref_sel, links[c], dims, mu)
+            if c == 0:
+                tc = time.perf_counter() - t
+            kap = kappa1(D, Z)
+            del D, Z
+            be = block_errors(sel_keep[c], ref_sel)
+            dc = drift_componentwise(drift_keep[c], ref_drift)
+            r = {"config": c, "kappa1_D": kap, "worst_block_rel_err": float(be.max()),
+                 "blocks_above_1e-10": int((be > TOL).sum()),
+                 "worst_block_err_vs_largest_block": normwise_error(sel_keep[c], ref_sel),
+                 "worst_drift_component_rel_err": float(dc.max()),
+                 "worst_drift_rel_err_per_link": float(drift_errors(drift_keep[c], ref_drift).max()),
+                 "pass": bool(be.max() <= TOL and dc.max() <= TOL)}
+            if c == 0 and plain is not None:
+                r["plain_worst_block_rel_err"] = float(block_errors(plain_sel0, ref_sel).max())
+                r["plain_worst_drift_component_rel_err"] = float(drift_componentwise(plain_drift0, ref_drift).max())
+                r["plain_pass"] = bool(r["plain_worst_block_rel_err"] <= TOL
+                                       and r["plain_worst_drift_component_rel_err"] <= TOL)
+            rows.append(r)
+            print(f"[bench] parity config {c}: worst block {r['worst_block_rel_err']:.2e}, worst drift "
+                  f"component {r['worst_drift_component_rel_err']:.2e}", file=sys.stderr, flush=True)
+        host = _host()
+        cpu = {"value": 1.0 / tc, "unit": "configs/s", "cores": host["blas_threads"], "kind": "oracle",
                "sample": "configuration 0 of the 64 (one 8^3x4 lattice): dense LAPACK inverse "
                          "(numpy), gather of the selected blocks, drift; "
-                         f"{tc:.1f} s on the host"}
-        be = block_errors(sel0, ref_sel)
-        parity = {"config": 0, "worst_block_rel_err": float(be.max()),
-                  "blocks_above_1e-10": int((be > 1e-10).sum()), "blocks": int(be.size),
-                  "worst_block_err_vs_largest_block": normwise_error(sel0, ref_sel),
-                  "worst_drift_rel_err_per_link": float(drift_errors(drift0, ref_drift).max()),
-                  "kappa1_D": kap, "tolerance": tolerance(kap),
-                  "pass": bool(be.max() <= tolerance(kap)
-                               and drift_errors(drift0, ref_drift).max() <= tolerance(kap))}
-        if plain is not None:
-            parity["plain_worst_block_rel_err"] = float(block_errors(plain_sel0, ref_sel).max())
-            parity["plain_worst_drift_rel_err_per_link"] = float(drift_errors(plain_drift0, ref_drift).max())
+                         f"{tc:.1f} s on the host", "host": host}
+        parity = {"tolerance": TOL,
+                  "metric": "every 3x3 block: ||dZ||_F/||Z||_F; every drift component: |dK| / "
+                            "max(|K|, 1e-6 max|K|)",
+                  "configs": [r["config"] for r in rows],
+                  "pass_count": sum(r["pass"] for r in rows), "checked": len(rows),
+                  "worst_block_rel_err": max(r["worst_block_rel_err"] for r in rows),
+                  "worst_drift_component_rel_err": max(r["worst_drift_component_rel_err"] for r in rows),
+                  "eager_equals_graph": bool(eager_same),
+                  "pass": all(r["pass"] for r in rows) and (plain is None or rows[0].get("plain_pass", True)),
+                  "rows": rows}
 
     avg_launch_ms = gemm_ms / max(launches, 1)
     achieved = gemm_flops / max(gemm_ms, 1e-9) / 1e9  # TFLOP/s
@@ -236,6 +306,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": dt / args.steps * 1e3,
+        "eager_ms_per_step": eager_dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,

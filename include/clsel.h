@@ -49,10 +49,12 @@ extern "C" {
 #define CL_EINVAL (-1)      /* bad argument: odd or < 4 extent, null pointer, batch < 1 */
 #define CL_ENOMEM (-2)      /* device or host allocation failed */
 #define CL_EORDER (-3)      /* call out of order, e.g. cl_selinv before cl_factor */
-#define CL_ESINGULAR (-4)   /* zero or non-finite pivot inside a supernode (per config) */
+#define CL_ESINGULAR (-4)   /* non-finite pivot, zero pivot without perturbation, or a singular
+                               low-rank correction matrix (per config) */
 #define CL_ENONFINITE (-5)  /* non-finite or singular link (per config) */
 #define CL_EHIP (-6)        /* a HIP runtime call failed */
 #define CL_ENODEV (-7)      /* no usable GPU */
+#define CL_ERANK (-8)       /* more perturbed pivots than the low-rank correction holds (per config) */
 
 typedef struct cl_plan_s* cl_plan;
 typedef struct cl_batch_s* cl_batch;
@@ -64,6 +66,10 @@ typedef struct {
   int32_t nb;             /* block width of the frontal Gauss-Jordan sweep (1..64, default 64) */
   int32_t time_cuts;      /* 1: separators may cut the time direction; 0 (default): never */
   int32_t gemm_tile;      /* output tile of the plain products: 0 auto (64 x 64), 64, 12864, 128 */
+  int32_t lowrank_cap;    /* perturbed pivots one configuration may have undone (0: default,
+                             64 per 24576 rows of D, at least 64; at most 1024) */
+  double pivot_floor;     /* pivot perturbation threshold in units of D's entries (0: default 0.3;
+                             negative: no perturbation). See cl_factor. */
 } cl_plan_opts;
 
 typedef struct {
@@ -77,6 +83,8 @@ typedef struct {
   double flops_factor_alg; /* standard block LU count: 8/3 p^3 + 8 s p^2 + 8 s^2 p per supernode */
   double flops_selinv_alg; /* standard selected inversion: 16/3 p^3 + 8 p^2 s + 16 s^2 p */
   double flops_dense_inverse; /* 8 N^3: what a full inverse would cost */
+  int32_t lowrank_cap;     /* columns of the low-rank correction (0: perturbation off) */
+  double pivot_floor;      /* pivot perturbation threshold (negative: off) */
 } cl_plan_info_t;
 
 /* Symbolic analysis of one lattice shape (host only, no device work). Every
@@ -107,10 +115,23 @@ int cl_batch_use_graph(cl_batch batch, int32_t enable);
 /* Assembles D for each configuration from `links_dev` (device, [B][V][4][3][3]
  * complex128, copied before the call returns control of it to the stream) and
  * m_host[b], mu_host[b], then runs the supernodal factorisation (partial
- * pivoting inside each supernode's own rows). Enqueues only. */
+ * pivoting inside each supernode's own rows). Enqueues only.
+ * Pivot perturbation: a pivot whose modulus, after partial pivoting, is below the plan's
+ * pivot_floor is raised to that modulus (its phase kept). This factorises
+ * D~ = D + sum_k delta_k e_{i_k} e_{j_k}^T, one rank-1 term per perturbed pivot, whose pivot
+ * blocks are well conditioned. cl_selinv undoes the change exactly with the
+ * Sherman-Morrison-Woodbury identity, so every result is that of D itself (Sec. 3: the
+ * selected entries of D^{-1} are computed exactly, not approximated); cl_solve does the same.
+ * A configuration with more perturbed pivots than the plan's lowrank_cap gets CL_ERANK. */
 int cl_factor(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host);
 /* Selected inversion (Takahashi / Erisman-Tinney recurrences in supernodal form):
- * the blocks of D^{-1} on the filled pattern, root to leaves. Enqueues only. */
+ * the blocks of D~^{-1} on the filled pattern, root to leaves, gathered on the pattern of
+ * D; then the low-rank correction of the perturbed pivots (see cl_factor):
+ *   D^{-1} = D~^{-1} - X C Y,  X = D~^{-1} U,  Y = V^T D~^{-1},  C = (I + V^T X)^{-1},
+ * with U = [-delta_k e_{i_k}] and V = [e_{j_k}]. X and Y come from r right and r left solves
+ * through the same frontal factors, each refined once against D~ itself (the residual is
+ * formed from the links); the r x r matrix C by Gauss-Jordan elimination with partial
+ * pivoting. A singular C sets CL_ESINGULAR. Enqueues only. */
 int cl_selinv(cl_batch batch);
 /* Drift K [B][V][4][8] complex128 into out_dev (device). Enqueues only. */
 int cl_drift(cl_batch batch, void* out_dev);
@@ -157,8 +178,10 @@ int cl_langevin_update(cl_batch batch, void* links_out_dev, const void* kf_dev, 
  * x_dev (device) are [B][N][ns] complex128 with row index 3*site + colour and the
  * right-hand sides contiguous. 1 <= ns <= 4096. The first call for a given ns builds
  * and checks its launch tables and allocates a workspace of 2 * (sum of front rows) * ns
- * complex128 per configuration; calls with the same ns reuse them. Enqueues only;
- * CL_EORDER before the first factorisation. */
+ * complex128 per configuration; calls with the same ns reuse them. With perturbed pivots
+ * (cl_factor) the solution of D~ is corrected to that of D: x = x~ - X C (V^T x~), with X and
+ * C of the last cl_selinv, so cl_solve needs cl_selinv first where the plan perturbs
+ * (CL_EORDER otherwise). Enqueues only; CL_EORDER before the first factorisation. */
 int cl_solve(cl_batch batch, const void* rhs_dev, int32_t ns, void* x_dev);
 /* Stochastic estimate of the selected blocks (Sec. 3, Eq. 7: the estimator that
  * selected inversion replaces): from noise columns xi and X = D^{-1} xi (cl_solve), both
@@ -176,7 +199,7 @@ int cl_drift_from_blocks(cl_batch batch, const void* blocks_dev, void* out_dev);
 int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host,
            void* selected_out_dev, void* drift_out_dev);
 /* Waits for the batch's work and copies one status per active configuration:
- * 0, CL_ESINGULAR or CL_ENONFINITE. Returns 0 or an API error. */
+ * 0, CL_ESINGULAR, CL_ENONFINITE or CL_ERANK. Returns 0 or an API error. */
 int cl_status(cl_batch batch, int32_t* per_config_host);
 /* Measurement support: with profiling on (eager path only), every launch of the
  * complex GEMM kernel in a selected mode is bracketed by HIP events on the batch
@@ -197,6 +220,9 @@ int cl_batch_profile_read(cl_batch batch, double* gemm_ms, double* gemm_flops, d
  * stream. NULL arrays are allowed only with cap == 0. */
 int cl_batch_profile_launches(cl_batch batch, int64_t cap, double* ms, double* flops,
                               double* bytes, int32_t* mode, int64_t* n);
+/* Number of perturbed pivots of each active configuration in the last factorisation
+ * (host array of batch entries; waits for the stream). */
+int cl_batch_perturbations(cl_batch batch, int32_t* per_config_host);
 /* Non-blocking: 1 if all work enqueued by the batch's last call has finished, 0 if
  * it is still running, negative on error. */
 int cl_batch_query(cl_batch batch);

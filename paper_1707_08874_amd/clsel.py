@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libclsel.so")
 
 CL_OK, CL_EINVAL, CL_ENOMEM, CL_EORDER = 0, -1, -2, -3
-CL_ESINGULAR, CL_ENONFINITE, CL_EHIP, CL_ENODEV = -4, -5, -6, -7
+CL_ESINGULAR, CL_ENONFINITE, CL_EHIP, CL_ENODEV, CL_ERANK = -4, -5, -6, -7, -8
 FRONT_FIELDS = ["id", "parent", "level", "npiv", "nstr", "p", "s", "H", "ld", "off", "site_off",
                 "nchild", "child0", "child1", "child2", "child3", "inv_off0", "inv_off1",
                 "inv_off2", "inv_off3", "rel_off", "nsteps", "fbuf", "zbuf", "r0", "r1", "r2", "r3"]
@@ -30,7 +30,8 @@ class ClselError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf_sites", ctypes.c_int32), ("max_pivot_rows", ctypes.c_int32),
-                ("nb", ctypes.c_int32), ("time_cuts", ctypes.c_int32), ("gemm_tile", ctypes.c_int32)]
+                ("nb", ctypes.c_int32), ("time_cuts", ctypes.c_int32), ("gemm_tile", ctypes.c_int32),
+                ("lowrank_cap", ctypes.c_int32), ("pivot_floor", ctypes.c_double)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -40,7 +41,8 @@ class PlanInfo(ctypes.Structure):
                 ("max_pivot_rows", ctypes.c_int32), ("pool_elems", ctypes.c_int64),
                 ("flops_factor", ctypes.c_double), ("flops_selinv", ctypes.c_double),
                 ("flops_factor_alg", ctypes.c_double), ("flops_selinv_alg", ctypes.c_double),
-                ("flops_dense_inverse", ctypes.c_double)]
+                ("flops_dense_inverse", ctypes.c_double), ("lowrank_cap", ctypes.c_int32),
+                ("pivot_floor", ctypes.c_double)]
 
 
 _lib = None
@@ -51,7 +53,7 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
            "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables",
            "cl_gauge_drift", "cl_langevin_update", "cl_solve", "cl_stochastic_blocks",
-           "cl_drift_from_blocks"]
+           "cl_drift_from_blocks", "cl_batch_perturbations"]
 
 
 def lib():
@@ -95,6 +97,7 @@ def lib():
         "cl_solve": (ctypes.c_int, [vp, vp, ctypes.c_int32, vp]),
         "cl_stochastic_blocks": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp]),
         "cl_drift_from_blocks": (ctypes.c_int, [vp, vp, vp]),
+        "cl_batch_perturbations": (ctypes.c_int, [vp, i32p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -118,11 +121,15 @@ class Plan:
     """Symbolic analysis of one lattice shape (cl_symbolic_ex)."""
 
     def __init__(self, dims, leaf_sites: int = 0, max_pivot_rows: int = 0, nb: int = 0,
-                 time_cuts: bool = False, gemm_tile: int = 0):
+                 time_cuts: bool = False, gemm_tile: int = 0, lowrank_cap: int = 0,
+                 pivot_floor: float = 0.0):
+        """pivot_floor: 0 takes the library default (0.3), a negative value turns pivot
+        perturbation (and its low-rank correction) off; lowrank_cap: 0 takes the default."""
         L = lib()
         self.dims = tuple(int(v) for v in dims)
         self._h = ctypes.c_void_p()
-        opts = PlanOpts(leaf_sites, max_pivot_rows, nb, 1 if time_cuts else 0, gemm_tile)
+        opts = PlanOpts(leaf_sites, max_pivot_rows, nb, 1 if time_cuts else 0, gemm_tile,
+                        lowrank_cap, float(pivot_floor))
         _check(L.cl_symbolic_ex(_dims(dims), ctypes.byref(opts), ctypes.byref(self._h)))
 
     def info(self) -> dict:
@@ -321,6 +328,12 @@ class Batch:
     def status(self) -> np.ndarray:
         out = np.zeros(self.active, dtype=np.int32)
         _check(lib().cl_status(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+    def perturbations(self) -> np.ndarray:
+        """Perturbed pivots of each active configuration in the last factorisation."""
+        out = np.zeros(self.active, dtype=np.int32)
+        _check(lib().cl_batch_perturbations(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
 
     def sync(self):

@@ -9,12 +9,14 @@
 //            inverses, transformed pivot rows);
 //   iws    : int32 workspace of iws_elems entries (pivot lists, row maps, row ids).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace clsel {
 
-// Pool selectors for plain GEMM operands.
-enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2, kPoolRhs = 3 };
+// Pool selectors for plain GEMM operands (kPoolExt: a caller's buffer, e.g. a solution).
+enum : int { kPool0 = 0, kPool1 = 1, kPoolWs = 2, kPoolRhs = 3, kPoolExt = 4 };
 
 // Front assembly: one entry per (front) of a level. Entries between two update rows
 // (the S x S block) are left to the Schur-complement GEMM, which sums the children's
@@ -40,6 +42,10 @@ struct PanelDesc {
   int64_t piv_off;        // iws: nb pivot rows (rows of the input front)
   int64_t rmap_off;       // iws: H entries, new row -> old row
   int64_t rowid_off;      // iws: p entries, equation currently at each pivot row
+  // pivot perturbation record (per pivot column of the front, Sigma p index space):
+  int64_t pdelta_off;     // ws: delta added to the pivot of column c at pdelta_off + c
+  int64_t peq_off;        // iws: global pivot index of the equation that pivots column c
+  int pbase;              // index of the front's pivot column 0 in that space (= rowid base)
   int H, p, ld, k, nbk;
 };
 
@@ -87,6 +93,8 @@ struct GatherDesc {
 // Solves D X = R through the frontal factors (R, X: n columns). Per front f the
 // right-hand-side workspace holds two H x n row-major blocks: R_f (assembled
 // right-hand side; its update rows later hold -X_S) at roff and X_f at xoff.
+// Left solves W D = G (n row vectors) use the same descriptors with the blocks stored
+// transposed, n x H row-major (a front's row I of right-hand side j at j * H + I).
 struct RhsAsmDesc {        // R_f = rhs on the pivot rows + the children's update rows
   int64_t roff;
   int64_t site_off;
@@ -95,18 +103,46 @@ struct RhsAsmDesc {        // R_f = rhs on the pivot rows + the children's updat
   int64_t inv_off[4];
   int64_t child_roff[4];
   int child_p[4];
+  int child_H[4];          // child front rows (the transposed layout's row length)
 };
-struct RhsGatherDesc {     // X_f[S] (and -X_f[S] into R_f[S]) from the parent's X
-  int64_t roff, xoff, par_xoff;
+struct RhsGatherDesc {     // X_f[S] (and -X_f[S] into R_f[S]; +X_f[S] for left solves)
+  int64_t roff, xoff, par_xoff;   // from the parent's X
   int64_t rel_off;
   int64_t blk_start;
-  int p, s;
+  int p, s, par_H;
 };
 struct SolScatterDesc {    // pivot rows of X_f to the solution vector
   int64_t xoff;
   int64_t site_off;
   int64_t blk_start;
-  int p;
+  int p, H;                // H: row length of the transposed (left-solve) layout
+};
+
+// Low-rank correction of the perturbed pivots (Sherman-Morrison-Woodbury). Per
+// configuration, ws holds from offset 0 the pivot-column deltas (N) and then the
+// correction's persistent buffers; iws holds after the row ids the pivot-column
+// equations (N) and the compacted list. All matrices are [N][R] row-major (R = cap),
+// columns >= the configuration's count are zero.
+struct SmwCtx {
+  double2* ws;
+  int64_t ws_stride;
+  int32_t* iws;
+  int64_t iws_stride;
+  int64_t pdelta_off;   // ws, N: delta of each pivot column (0: not perturbed)
+  int64_t x_off;        // ws, N x R: X = D~^{-1} U
+  int64_t y_off;        // ws, N x R: Y^T = D~^{-T} V (rows of D~^{-1}, transposed)
+  int64_t xc_off;       // ws, N x R: X C
+  int64_t r_off;        // ws, N x R: right-hand sides and residuals; R x R scratch of C
+  int64_t c_off;        // ws, R x R: C = (I + V^T X)^{-1}
+  int64_t dl_off;       // ws, R: delta_k
+  int64_t peq_off;      // iws, N: pivot index (into pivot_global) of each column's equation
+  int64_t li_off;       // iws, R: global row i_k
+  int64_t lj_off;       // iws, R: global column j_k
+  int64_t cnt_off;      // iws, 1: perturbations of the configuration (capped at R)
+  const int32_t* pivot_global;  // [N]: global matrix index of each pivot column
+  int64_t n;
+  int R;
+  int32_t* status;
 };
 
 }  // namespace clsel

@@ -49,11 +49,14 @@ struct GemmCtx {
   double2* rhs;         // right-hand-side workspace of the solves (pool kPoolRhs)
   int64_t rhs_stride;
   const int32_t* inv_maps;  // plan: front row -> child update row (Schur with has_c0 = 2)
+  double2* ext;             // a caller's buffer (pool kPoolExt), per-configuration stride
+  int64_t ext_stride;
 };
 
 __device__ __forceinline__ double2* pool_ptr(const GemmCtx& g, int b, int pool) {
   if (pool == kPoolWs) return g.ws + b * g.ws_stride;
   if (pool == kPoolRhs) return g.rhs + b * g.rhs_stride;
+  if (pool == kPoolExt) return g.ext + b * g.ext_stride;
   return g.fronts + b * g.cfg_stride + (int64_t)pool * g.pool_elems;
 }
 
@@ -439,8 +442,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
-                 int64_t rhs_stride, const int32_t* inv_maps) {
-  GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride, rhs, rhs_stride, inv_maps};
+                 int64_t rhs_stride, const int32_t* inv_maps, double2* ext, int64_t ext_stride) {
+  GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride, rhs, rhs_stride, inv_maps,
+            ext, ext_stride};
   const dim3 blk(kGemmThreads);
   if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
   else if (mode == 0 && tile == kTile128x64) hipLaunchKernelGGL((k_gemm<0, 4, 2, 16, 1>), grid, blk, 0, st, descs, ndesc, g);

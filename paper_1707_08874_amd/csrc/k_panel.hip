@@ -12,6 +12,13 @@
 //            Gauss-Jordan elimination without further pivoting in LDS;
 //   and records the row permutation of the step and the equation held by each
 //   pivot row (needed to put the columns of the inverse back in natural order).
+// Pivot perturbation: where the chosen pivot's modulus is below `floor` (> 0) it is
+// raised to `floor` with its phase kept. Row operations only ever subtract multiples of
+// other rows, so adding delta to the current pivot entry is adding delta to the entry
+// of D at (the pivot row's equation, the pivot column): the sweep factorises that
+// perturbed matrix, consistently in both phases (phase 2 adds the same delta to Pi).
+// Each pivot column records its delta (zero if none) and the equation that pivots it;
+// the selected inversion undoes the perturbations with a low-rank correction.
 // One work-group of 512 threads per (front, configuration).
 #include "desc.hpp"
 #include "device.hpp"
@@ -83,7 +90,7 @@ template <int RPT>
 __global__ void __launch_bounds__(kPanelThreads)
 k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts, int64_t cfg_stride,
         double2* __restrict__ ws, int64_t ws_stride, int32_t* __restrict__ iws, int64_t iws_stride,
-        int32_t* __restrict__ status) {
+        int32_t* __restrict__ status, double floor) {
   const PanelDesc d = descs[blockIdx.x];
   const int b = blockIdx.y;
   const int tid = threadIdx.x;
@@ -97,6 +104,7 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   __shared__ double s_rv[2][kWaves];
   __shared__ int s_ri[2][kWaves];
   __shared__ int s_piv[kMaxNB];
+  __shared__ double2 s_delta[kMaxNB];  // perturbation of each pivot of the block
   __shared__ int s_flag;
   __shared__ double2 s_pcol[2][kMaxNB];
   __shared__ double2 s_buf[kMaxNB * kPiLd];
@@ -165,12 +173,25 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
         const double2* pv = s_cand[par][ww];
         if (tid == 0) {
           s_piv[g0 + c] = pr;
-          if (!(bb > 0.0) || !isfinite(bb)) s_flag = 1;
+          if (!isfinite(bb) || (!(bb > 0.0) && !(floor > 0.0))) s_flag = 1;
         }
 #pragma unroll
         for (int j = 0; j < RPT; ++j) used[j] = used[j] || (tid + j * kPanelThreads == pr);
         double2 dp = pv[0];
-        if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) dp = make_double2(1.0, 0.0);
+        const bool finite = isfinite(dp.x) && isfinite(dp.y);
+        double2 delta = make_double2(0.0, 0.0);
+        if (floor > 0.0 && finite && cabs2(dp) < floor * floor) {
+          // raise the modulus to floor, keeping the phase (a zero pivot becomes floor)
+          const double a = sqrt(cabs2(dp));
+          const double2 up = a > 0.0 ? cscale(dp, floor / a) : make_double2(floor, 0.0);
+          delta = csub(up, dp);
+          dp = up;
+        }
+        if (tid == 0) {
+          s_delta[g0 + c] = delta;
+          if (!finite) s_flag = 1;
+        }
+        if (!(cabs2(dp) > 0.0) || !finite) dp = make_double2(1.0, 0.0);
         const double2 invd = crecip(dp);
         // rows out of the elimination (pivots, rows past the candidates) take a zero
         // multiplier and only rotate; their values are not read again
@@ -268,6 +289,7 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
     for (int q = 0; q < 8; ++q) {
       const int cc = cg * 8 + q;
       v[q] = (live && cc < nbk) ? Xp[(int64_t)s_piv[t] * ld + cc] : make_double2(0.0, 0.0);
+      if (live && cc == t) v[q] = cadd(v[q], s_delta[t]);  // the perturbed pivot, as in phase 1
     }
     for (int c = 0; c < nbk; ++c) {
       const int par = c & 1;
@@ -309,8 +331,12 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   }
   __syncthreads();
 
-  // ---- pivot list, row map of this step, equation ids of the pivot rows
-  if (tid < nbk) IW[d.piv_off + tid] = k + s_piv[tid];
+  // ---- pivot list, perturbation record, row map of this step, equation ids of the pivot rows
+  if (tid < nbk) {
+    IW[d.piv_off + tid] = k + s_piv[tid];
+    ws[b * ws_stride + d.pdelta_off + k + tid] = s_delta[tid];
+    IW[d.peq_off + k + tid] = d.pbase + IW[d.rowid_off + k + s_piv[tid]];
+  }
   for (int i = tid; i < cand; i += kPanelThreads) { s_at[i] = i; s_pos[i] = i; }
   __syncthreads();
   if (tid == 0) {
@@ -332,11 +358,11 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
 
 void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs, const double2* fronts,
                   int64_t cfg_stride, double2* ws, int64_t ws_stride, int32_t* iws,
-                  int64_t iws_stride, int32_t* status) {
+                  int64_t iws_stride, int32_t* status, double floor) {
   switch (rpt) {
-    case 1: hipLaunchKernelGGL(k_panel<1>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status); break;
-    case 2: hipLaunchKernelGGL(k_panel<2>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status); break;
-    default: hipLaunchKernelGGL(k_panel<3>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status); break;
+    case 1: hipLaunchKernelGGL(k_panel<1>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status, floor); break;
+    case 2: hipLaunchKernelGGL(k_panel<2>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status, floor); break;
+    default: hipLaunchKernelGGL(k_panel<3>, grid, dim3(kPanelThreads), 0, st, descs, fronts, cfg_stride, ws, ws_stride, iws, iws_stride, status, floor); break;
   }
 }
 

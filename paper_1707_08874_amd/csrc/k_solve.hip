@@ -11,6 +11,9 @@
 // R_f[S], and X_f[J] = [A_JJ^{-1} | U^] [R_f[J]; -X_f[S]] = A_JJ^{-1} R_J - U^ X_S.
 // The products are GEMM launches; the kernels here move rows between fronts.
 // One thread per (row, column) element; consecutive threads take consecutive columns.
+// Left solves (row vectors, W D = G) run the transposed recurrences with the same
+// factors: forward G_f[S] -= G_f[J] U^, backward W_J = G_J A_JJ^{-1} - W_S L^, on front
+// blocks stored n x H (TRANS).
 #include "desc.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
@@ -27,6 +30,14 @@ __device__ __forceinline__ int find_desc(const Desc* d, int n, int64_t blk) {
   return lo;
 }
 
+// Element (row I, right-hand side j) of a front block of H rows: row-major H x ns for
+// right solves, ns x H (TRANS) for left solves.
+template <bool TRANS>
+__device__ __forceinline__ int64_t rhs_at(int64_t off, int I, int j, int H, int ns) {
+  return TRANS ? off + (int64_t)j * H + I : off + (int64_t)I * ns + j;
+}
+
+template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_rhs_assemble(const RhsAsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ rhs,
                int64_t rhs_stride, const double2* __restrict__ b, int64_t b_stride,
@@ -44,11 +55,15 @@ k_rhs_assemble(const RhsAsmDesc* __restrict__ descs, int ndesc, double2* __restr
   }
   for (int c = 0; c < d.nchild; ++c) {
     const int ii = inv_maps[d.inv_off[c] + I];
-    if (ii >= 0) v = cadd(v, R[d.child_roff[c] + (int64_t)(d.child_p[c] + ii) * ns + col]);
+    if (ii >= 0) {
+      const int chH = d.child_H[c];
+      v = cadd(v, R[rhs_at<TRANS>(d.child_roff[c], d.child_p[c] + ii, col, chH, ns)]);
+    }
   }
-  R[d.roff + (int64_t)I * ns + col] = v;
+  R[rhs_at<TRANS>(d.roff, I, col, d.H, ns)] = v;
 }
 
+template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_rhs_gather(const RhsGatherDesc* __restrict__ descs, int ndesc, double2* __restrict__ rhs,
              int64_t rhs_stride, const int32_t* __restrict__ rel_maps, int ns) {
@@ -58,25 +73,40 @@ k_rhs_gather(const RhsGatherDesc* __restrict__ descs, int ndesc, double2* __rest
   if (e >= (int64_t)d.s * ns) return;
   const int r = (int)(e / ns), col = (int)(e - (e / ns) * ns);
   double2* R = rhs + cfg * rhs_stride;
-  const double2 x = R[d.par_xoff + (int64_t)rel_maps[d.rel_off + r] * ns + col];
-  const int64_t row = (int64_t)(d.p + r) * ns + col;
-  R[d.xoff + row] = x;
-  R[d.roff + row] = make_double2(-x.x, -x.y);
+  const int H = d.p + d.s;
+  const double2 x = R[rhs_at<TRANS>(d.par_xoff, rel_maps[d.rel_off + r], col, d.par_H, ns)];
+  R[rhs_at<TRANS>(d.xoff, d.p + r, col, H, ns)] = x;
+  // right solves: X_J = [A_JJ^{-1} | U^] [R_J; -X_S]; left solves: W_J = [G_J | W_S] [A_JJ^{-1}; -L^]
+  R[rhs_at<TRANS>(d.roff, d.p + r, col, H, ns)] = TRANS ? x : make_double2(-x.x, -x.y);
 }
 
+template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_sol_scatter(const SolScatterDesc* __restrict__ descs, int ndesc, const double2* __restrict__ rhs,
               int64_t rhs_stride, double2* __restrict__ x, int64_t x_stride,
-              const int32_t* __restrict__ front_sites, int ns) {
+              const int32_t* __restrict__ front_sites, int ns, int accumulate) {
   const int cfg = blockIdx.y;
   const SolScatterDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.p * ns) return;
   const int I = (int)(e / ns), col = (int)(e - (e / ns) * ns);
   const int site = front_sites[d.site_off + I / 3];
-  x[cfg * x_stride + ((int64_t)site * 3 + I % 3) * ns + col] =
-      rhs[cfg * rhs_stride + d.xoff + (int64_t)I * ns + col];
+  double2 v = rhs[cfg * rhs_stride + rhs_at<TRANS>(d.xoff, I, col, d.H, ns)];
+  double2* dst = x + cfg * x_stride + ((int64_t)site * 3 + I % 3) * ns + col;
+  if (accumulate) v = cadd(v, *dst);
+  *dst = v;
 }
+
+template __global__ void k_rhs_assemble<false>(const RhsAsmDesc*, int, double2*, int64_t, const double2*,
+                                               int64_t, const int32_t*, const int32_t*, int);
+template __global__ void k_rhs_assemble<true>(const RhsAsmDesc*, int, double2*, int64_t, const double2*,
+                                              int64_t, const int32_t*, const int32_t*, int);
+template __global__ void k_rhs_gather<false>(const RhsGatherDesc*, int, double2*, int64_t, const int32_t*, int);
+template __global__ void k_rhs_gather<true>(const RhsGatherDesc*, int, double2*, int64_t, const int32_t*, int);
+template __global__ void k_sol_scatter<false>(const SolScatterDesc*, int, const double2*, int64_t, double2*,
+                                              int64_t, const int32_t*, int, int);
+template __global__ void k_sol_scatter<true>(const SolScatterDesc*, int, const double2*, int64_t, double2*,
+                                             int64_t, const int32_t*, int, int);
 
 // Z~_{x,y} = (1/n) sum_s X_{x,s} xi_{y,s}^*, y in {x, x+nu, x-nu} (periodic sites),
 // written in the slot order of the selected blocks. One thread per (site, slot, entry).

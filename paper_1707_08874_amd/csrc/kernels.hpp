@@ -19,6 +19,7 @@ constexpr int kKChunk = 128;
 constexpr int kMaxChunks = 12;        // longer K: chunks of ceil(K / kMaxChunks) products (whole stages)
 // front assembly and Z_SS gather: tile of one 256-thread work-group (one column per thread)
 constexpr int kAsmTileRows = 8, kAsmTileCols = 256;
+constexpr int kMaxLowRank = 1024;     // columns of the low-rank correction
 constexpr int32_t kStatusSingular = -4;
 constexpr int32_t kStatusNonFinite = -5;
 
@@ -50,23 +51,37 @@ __global__ void k_langevin_update(const double2* links_in, double2* links_out, c
                                   const double* kref, const unsigned long long* kmax_bits,
                                   int64_t V, double* eps_out);
 
+template <bool TRANS>
 __global__ void k_rhs_assemble(const RhsAsmDesc* descs, int ndesc, double2* rhs, int64_t rhs_stride,
                                const double2* b, int64_t b_stride, const int32_t* front_sites,
                                const int32_t* inv_maps, int ns);
+template <bool TRANS>
 __global__ void k_rhs_gather(const RhsGatherDesc* descs, int ndesc, double2* rhs, int64_t rhs_stride,
                              const int32_t* rel_maps, int ns);
+template <bool TRANS>
 __global__ void k_sol_scatter(const SolScatterDesc* descs, int ndesc, const double2* rhs,
                               int64_t rhs_stride, double2* x, int64_t x_stride,
-                              const int32_t* front_sites, int ns);
+                              const int32_t* front_sites, int ns, int accumulate);
 __global__ void k_stochastic_blocks(const double2* x, const double2* xi, LatticeDims dims, int64_t V,
                                     int ns, double2* out);
 
+__global__ void k_smw_list(SmwCtx c);
+__global__ void k_smw_rhs(SmwCtx c, int which);
+__global__ void k_smw_residual(SmwCtx c, const double2* links, const double2* linv, const double* mvals,
+                               const double* muvals, LatticeDims dims, int64_t V, int trans);
+__global__ void k_smw_residual_delta(SmwCtx c, int trans);
+__global__ void k_smw_capacitance(SmwCtx c);
+__global__ void k_smw_correct(SmwCtx c, double2* sel, LatticeDims dims, int64_t V);
+__global__ void k_smw_gather_rows(SmwCtx c, const double2* x, int64_t x_stride, double2* t,
+                                  int64_t t_stride, int ns);
+
 void launch_panel(int rpt, dim3 grid, hipStream_t st, const PanelDesc* descs,
                   const double2* fronts, int64_t cfg_stride, double2* ws, int64_t ws_stride,
-                  int32_t* iws, int64_t iws_stride, int32_t* status);
+                  int32_t* iws, int64_t iws_stride, int32_t* status, double floor);
 void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
-                 int64_t rhs_stride, const int32_t* inv_maps);
+                 int64_t rhs_stride, const int32_t* inv_maps, double2* ext = nullptr,
+                 int64_t ext_stride = 0);
 
 }  // namespace clsel

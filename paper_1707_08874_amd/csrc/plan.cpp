@@ -119,6 +119,10 @@ int build_plan(const int32_t dims[4], const PlanOptions& opt, Plan& P, std::stri
     err = "invalid plan options";
     return -1;
   }
+  if (opt.lowrank_cap < 0 || opt.lowrank_cap > 1024 || !(opt.pivot_floor == opt.pivot_floor)) {
+    err = "invalid plan options (lowrank_cap must be 0..1024, pivot_floor a number)";
+    return -1;
+  }
   P = Plan();
   P.opt = opt;
   int L[4];
@@ -135,6 +139,8 @@ int build_plan(const int32_t dims[4], const PlanOptions& opt, Plan& P, std::stri
   }
   P.V = (int64_t)L[0] * L[1] * L[2] * L[3];
   P.N = 3 * P.V;
+  if (P.opt.lowrank_cap == 0) P.opt.lowrank_cap = default_lowrank_cap(P.N);
+  if (P.opt.pivot_floor < 0) P.opt.lowrank_cap = 0;
 
   // 1. separator tree of the whole torus
   std::vector<SepNode> nodes;

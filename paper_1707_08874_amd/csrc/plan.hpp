@@ -24,7 +24,22 @@ struct PlanOptions {
   int nb = 64;              // block width of the frontal Gauss-Jordan sweep
   int time_cuts = 0;        // 0: separators never cut the time direction, 1: allowed
   int gemm_tile = 0;        // plain-product tile: 0 auto (64), 64, 12864 (128 x 64) or 128
+  // Pivots of modulus below pivot_floor are raised to it during the factorisation, and
+  // the rank-r change of D this makes is undone exactly afterwards by a low-rank
+  // (Sherman-Morrison-Woodbury) correction with at most lowrank_cap columns per
+  // configuration. pivot_floor < 0: no perturbation, pivoting inside supernodes only.
+  double pivot_floor = 0.3;
+  int lowrank_cap = 0;      // 0: default_lowrank_cap(N)
 };
+
+// Default number of perturbed pivots one configuration can have undone: 64 per 24576
+// matrix rows (8192 sites), at least 64. Measured counts at the default floor: 0 to 26
+// on 8^3x4 configurations, 31 on a 12^3x6 one; most come from the leaf supernodes, whose
+// number grows with the volume.
+inline int default_lowrank_cap(int64_t n) {
+  const int64_t c = 64 * ((n + 24575) / 24576);
+  return (int)(c < 64 ? 64 : (c > 1024 ? 1024 : c));
+}
 
 struct Front {
   int id = -1;

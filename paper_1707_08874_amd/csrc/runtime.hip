@@ -62,6 +62,15 @@ struct Layout {
   int64_t sel_elems = 0;    // V*81
   std::vector<char> blob;
   std::vector<Launch> factor, selinv;
+  // low-rank correction of perturbed pivots: R columns (0: off), persistent regions at the
+  // start of ws and iws (see clsel::SmwCtx), the global index of every pivot column, the
+  // X C product, and the rows of the right-hand-side workspace its solves need
+  int R = 0;
+  int64_t pdelta_off = 0, x_off = 0, y_off = 0, xc_off = 0, r_off = 0, c_off = 0, dl_off = 0;
+  int64_t peq_off = 0, li_off = 0, lj_off = 0, cnt_off = 0;
+  std::vector<int32_t> pivot_global;
+  Launch smw_xc{};
+  int64_t sum_H = 0;        // rows of all fronts (a solve workspace holds 2 * sum_H * ns)
 };
 
 size_t blob_push(std::vector<char>& blob, const void* p, size_t n) {
@@ -103,12 +112,38 @@ void build_layout(const clsel::Plan& P, Layout& L) {
   L.cfg_stride = 2 * pool;
   L.links_elems = P.V * 36;
   L.sel_elems = P.V * 81;
-  // persistent int region: row ids of every front's pivot rows
+  // persistent int region: row ids of every front's pivot rows, then the equation that
+  // pivots each pivot column, then the perturbation list (rows, columns, count, total)
   std::vector<int64_t> rowid_base(P.fronts.size());
   int64_t acc = 0;
   for (size_t f = 0; f < P.fronts.size(); ++f) { rowid_base[f] = acc; acc += P.fronts[f].p; }
-  const int64_t istep0 = (acc + 63) & ~int64_t(63);
-  int64_t ws_max = 0, iws_max = istep0;
+  auto r64 = [](int64_t v) { return (v + 63) & ~int64_t(63); };
+  const int R = P.opt.lowrank_cap > 0 ? (int)std::min<int64_t>(P.opt.lowrank_cap, P.N) : 0;
+  L.R = R;
+  L.peq_off = r64(acc);
+  L.li_off = L.peq_off + r64(acc);
+  L.lj_off = L.li_off + r64(R);
+  L.cnt_off = L.lj_off + r64(R);
+  const int64_t istep0 = L.cnt_off + 64;
+  // persistent complex region: pivot deltas, then the correction's matrices
+  auto r16 = [](int64_t v) { return (v + 15) & ~int64_t(15); };
+  L.pdelta_off = 0;
+  L.x_off = r16(P.N);
+  L.y_off = L.x_off + r16(P.N * R);
+  L.xc_off = L.y_off + r16(P.N * R);
+  L.r_off = L.xc_off + r16(P.N * R);
+  L.c_off = L.r_off + r16(P.N * R);
+  L.dl_off = L.c_off + r16((int64_t)R * R);
+  const int64_t ws0 = L.dl_off + r16(R);
+  L.pivot_global.assign(acc, 0);
+  L.sum_H = 0;
+  for (size_t f = 0; f < P.fronts.size(); ++f) {
+    const clsel::Front& fr = P.fronts[f];
+    L.sum_H += fr.H;
+    for (int c = 0; c < fr.p; ++c)
+      L.pivot_global[rowid_base[f] + c] = 3 * P.front_sites[fr.site_off + c / 3] + c % 3;
+  }
+  int64_t ws_max = ws0, iws_max = istep0;
 
   for (size_t lev = 0; lev < P.levels.size(); ++lev) {
     const std::vector<int>& fl = P.levels[lev];
@@ -142,7 +177,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
     for (int q = 0; q < steps; ++q) {
       std::vector<clsel::PanelDesc> pd;
       std::vector<clsel::GemmDesc> g1, g2;
-      int64_t wso = 0, iwo = istep0, t1 = 0, t2 = 0;
+      int64_t wso = ws0, iwo = istep0, t1 = 0, t2 = 0;
       int rpt = 1;
       for (int f : fl) {
         const clsel::Front& fr = P.fronts[f];
@@ -160,6 +195,9 @@ void build_layout(const clsel::Plan& P, Layout& L) {
         p.rmap_off = iwo; iwo += fr.H;
         iwo = (iwo + 63) & ~int64_t(63);
         p.rowid_off = rowid_base[f];
+        p.pdelta_off = L.pdelta_off + rowid_base[f];
+        p.peq_off = L.peq_off + rowid_base[f];
+        p.pbase = (int)rowid_base[f];
         p.H = fr.H; p.p = fr.p; p.ld = fr.ld; p.k = k; p.nbk = nbk;
         pd.push_back(p);
         clsel::GemmDesc a{};
@@ -286,6 +324,16 @@ void build_layout(const clsel::Plan& P, Layout& L) {
   }
   L.ws_elems = std::max<int64_t>(ws_max, 16);
   L.iws_elems = iws_max;
+  if (R > 0) {  // X C = X * C, [N][R] = [N][R] [R][R]
+    std::vector<clsel::GemmDesc> g(1);
+    clsel::GemmDesc& d = g[0];
+    d.mode = 0; d.M = (int)P.N; d.N = R; d.K = R;
+    d.a_pool = clsel::kPoolWs; d.a_off = L.x_off; d.lda = R;
+    d.b_pool = clsel::kPoolWs; d.b_off = L.c_off; d.ldb = R;
+    d.c_pool = clsel::kPoolWs; d.c_off = L.xc_off; d.ldc = R;
+    d.alpha = 1.0; d.has_c0 = 0; d.kblock = 0;
+    L.smw_xc = gemm_launch(L.blob, g, 0, clsel::kTile64);
+  }
   for (std::vector<Launch>* ls : {&L.factor, &L.selinv})
     for (Launch& l : *ls) {
       if (l.kind != kGemm) continue;
@@ -346,6 +394,12 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
         REQ(d[i].piv_off + d[i].nbk <= L.iws_elems, "panel piv", d[i].piv_off, L.iws_elems);
         REQ(d[i].rmap_off + d[i].H <= L.iws_elems, "panel rmap", d[i].rmap_off, L.iws_elems);
         REQ(d[i].rowid_off + d[i].p <= rowid_total, "panel rowid", d[i].rowid_off, rowid_total);
+        REQ(d[i].pbase == d[i].rowid_off && d[i].pdelta_off == L.pdelta_off + d[i].pbase &&
+            d[i].peq_off == L.peq_off + d[i].pbase, "panel perturbation record", d[i].pbase, 0);
+        REQ(d[i].pdelta_off + d[i].p <= L.pdelta_off + P.N && L.pdelta_off + P.N <= L.x_off,
+            "panel deltas", d[i].pdelta_off, L.x_off);
+        REQ(d[i].peq_off + d[i].p <= L.peq_off + P.N && L.peq_off + P.N <= L.li_off, "panel equations",
+            d[i].peq_off, L.li_off);
       }
     }
   }
@@ -414,6 +468,14 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
     return true;
   };
   if (!check_gemms(L.factor) || !check_gemms(L.selinv)) return false;
+  if (L.R > 0) {
+    if (!check_gemms(std::vector<Launch>{L.smw_xc})) return false;
+    REQ((int64_t)L.pivot_global.size() == P.N, "pivot table", (int64_t)L.pivot_global.size(), P.N);
+    for (int32_t g : L.pivot_global) REQ(g >= 0 && g < P.N, "pivot table entry", g, P.N);
+    REQ(L.R <= clsel::kMaxLowRank && L.R <= P.N, "low-rank columns", L.R, clsel::kMaxLowRank);
+    REQ(L.dl_off + L.R <= L.ws_elems && L.cnt_off + 2 <= L.iws_elems, "low-rank regions", L.dl_off, L.ws_elems);
+    REQ((int64_t)L.R * L.R <= P.N * L.R, "capacitance scratch", (int64_t)L.R * L.R, P.N * L.R);
+  }
   for (const Launch& l : L.selinv) {
     if (l.kind != kZss) continue;
     const clsel::GatherDesc* d = (const clsel::GatherDesc*)(L.blob.data() + l.desc_off);
@@ -447,6 +509,9 @@ size_t layout_bytes(const clsel::Plan& P, const Layout& L, int64_t B) {
   b += L.blob.size();
   b += P.front_sites.size() * 4 + P.inv_maps.size() * 4 + P.rel_maps.size() * 4;
   b += P.sel_off.size() * 8 + P.sel_ld.size() * 4;
+  // the low-rank correction's solve workspace (R right-hand sides) and pivot table
+  b += (size_t)B * 2 * L.sum_H * L.R * 16;
+  b += L.pivot_global.size() * 4;
   return b;
 }
 
@@ -462,25 +527,36 @@ enum SolveKind { kRhsAsm = 10, kRhsGather, kSolScatter };
 
 struct SolveLayout {
   int ns = 0;               // right-hand sides
+  bool trans = false;       // left solves (row vectors): front blocks stored ns x H
   int64_t rhs_elems = 0;    // complex workspace per configuration: R and X blocks
+  int64_t stride = 0;       // per-configuration stride of the workspace (rhs_elems + extra)
+  int64_t t_off = 0;        // extra region: rows j_k of the solution (R x ns), if any
   std::vector<char> blob;
   std::vector<Launch> fwd, bwd;
   Launch scatter{};
+  Launch corr{};            // x -= (X C) T: the low-rank correction of a solution (gridx 0: none)
 };
 
 // Launch tables of X = D^{-1} R (see k_solve.hip): per level, leaves first, the
 // right-hand-side assembly and R_S += -L^ R_J; then per level, root first, the gather of
 // X_S and X_J = [A_JJ^{-1} | U^] [R_J; -X_S]; then the pivot rows to the solution.
-void build_solve_layout(const clsel::Plan& P, int ns, SolveLayout& S) {
+// Left solves W = G D^{-1} (trans): G_S -= G_J U^ forward, W_J = [G_J | W_S] [A_JJ^{-1}; -L^]
+// backward, with the front blocks stored ns x H. With lowrank > 0 the workspace has room
+// for T = rows j_k of the solution and corr holds x -= (X C) T (right solves only).
+void build_solve_layout(const clsel::Plan& P, const Layout& L, int ns, bool trans, int lowrank,
+                        SolveLayout& S) {
   S = SolveLayout{};
   S.ns = ns;
+  S.trans = trans;
   const size_t nf = P.fronts.size();
   std::vector<int64_t> roff(nf), xoff(nf);
   int64_t acc = 0;
   for (size_t f = 0; f < nf; ++f) { roff[f] = acc; acc += (int64_t)P.fronts[f].H * ns; }
   for (size_t f = 0; f < nf; ++f) xoff[f] = acc + roff[f];
   S.rhs_elems = 2 * acc;
-  const int64_t pool = P.pool_elems;
+  S.t_off = S.rhs_elems;
+  S.stride = S.rhs_elems + (int64_t)lowrank * ns;
+  const int tr = trans ? 1 : 0;
   for (size_t lev = 0; lev < P.levels.size(); ++lev) {
     std::vector<clsel::RhsAsmDesc> ad;
     std::vector<clsel::GemmDesc> gs;
@@ -497,22 +573,32 @@ void build_solve_layout(const clsel::Plan& P, int ns, SolveLayout& S) {
         d.inv_off[c] = fr.inv_off[c];
         d.child_roff[c] = roff[fr.child[c]];
         d.child_p[c] = P.fronts[fr.child[c]].p;
+        d.child_H[c] = P.fronts[fr.child[c]].H;
       }
       ad.push_back(d);
       if (fr.s == 0) continue;
-      clsel::GemmDesc g{};  // R[S] += (-L^) R[J]
-      g.mode = 0; g.M = fr.s; g.N = ns; g.K = fr.p;
-      g.a_pool = fr.fbuf; g.a_off = fr.off + (int64_t)fr.p * fr.ld; g.lda = fr.ld;
-      g.b_pool = clsel::kPoolRhs; g.b_off = roff[f]; g.ldb = ns;
-      g.c_pool = clsel::kPoolRhs; g.c_off = roff[f] + (int64_t)fr.p * ns; g.ldc = ns;
-      g.c0_pool = clsel::kPoolRhs; g.c0_off = g.c_off; g.ldc0 = ns;
-      g.alpha = 1.0; g.has_c0 = 1;
+      clsel::GemmDesc g{};
+      g.mode = 0;
+      if (!trans) {  // R[S] += (-L^) R[J]
+        g.M = fr.s; g.N = ns; g.K = fr.p;
+        g.a_pool = fr.fbuf; g.a_off = fr.off + (int64_t)fr.p * fr.ld; g.lda = fr.ld;
+        g.b_pool = clsel::kPoolRhs; g.b_off = roff[f]; g.ldb = ns;
+        g.c_pool = clsel::kPoolRhs; g.c_off = roff[f] + (int64_t)fr.p * ns; g.ldc = ns;
+        g.alpha = 1.0;
+      } else {       // G[:, S] -= G[:, J] U^
+        g.M = ns; g.N = fr.s; g.K = fr.p;
+        g.a_pool = clsel::kPoolRhs; g.a_off = roff[f]; g.lda = fr.H;
+        g.b_pool = fr.fbuf; g.b_off = fr.off + fr.p; g.ldb = fr.ld;
+        g.c_pool = clsel::kPoolRhs; g.c_off = roff[f] + fr.p; g.ldc = fr.H;
+        g.alpha = -1.0;
+      }
+      g.c0_pool = g.c_pool; g.c0_off = g.c_off; g.ldc0 = g.ldc;
+      g.has_c0 = 1;
       gs.push_back(g);
     }
-    S.fwd.push_back({kRhsAsm, blob_push(S.blob, ad.data(), ad.size() * sizeof(ad[0])), (int)ad.size(), blk, 0});
+    S.fwd.push_back({kRhsAsm, blob_push(S.blob, ad.data(), ad.size() * sizeof(ad[0])), (int)ad.size(), blk, tr});
     if (!gs.empty()) S.fwd.push_back(gemm_launch(S.blob, gs, 0, clsel::kTile64));
   }
-  (void)pool;
   for (int lev = (int)P.levels.size() - 1; lev >= 0; --lev) {
     std::vector<clsel::RhsGatherDesc> gd;
     std::vector<clsel::GemmDesc> gs;
@@ -524,37 +610,80 @@ void build_solve_layout(const clsel::Plan& P, int ns, SolveLayout& S) {
         d.roff = roff[f]; d.xoff = xoff[f]; d.par_xoff = xoff[fr.parent];
         d.rel_off = fr.rel_off; d.blk_start = blk;
         blk += cdiv64((int64_t)fr.s * ns, 256);
-        d.p = fr.p; d.s = fr.s;
+        d.p = fr.p; d.s = fr.s; d.par_H = P.fronts[fr.parent].H;
         gd.push_back(d);
       }
-      clsel::GemmDesc g{};  // X[J] = [A_JJ^{-1} | U^] [R_J; -X_S]
-      g.mode = 0; g.M = fr.p; g.N = ns; g.K = fr.H;
-      g.a_pool = fr.fbuf; g.a_off = fr.off; g.lda = fr.ld;
-      g.b_pool = clsel::kPoolRhs; g.b_off = roff[f]; g.ldb = ns;
-      g.c_pool = clsel::kPoolRhs; g.c_off = xoff[f]; g.ldc = ns;
+      clsel::GemmDesc g{};
+      g.mode = 0;
+      if (!trans) {  // X[J] = [A_JJ^{-1} | U^] [R_J; -X_S]
+        g.M = fr.p; g.N = ns; g.K = fr.H;
+        g.a_pool = fr.fbuf; g.a_off = fr.off; g.lda = fr.ld;
+        g.b_pool = clsel::kPoolRhs; g.b_off = roff[f]; g.ldb = ns;
+        g.c_pool = clsel::kPoolRhs; g.c_off = xoff[f]; g.ldc = ns;
+      } else {       // W[:, J] = [G_J | W_S] [A_JJ^{-1}; -L^]
+        g.M = ns; g.N = fr.p; g.K = fr.H;
+        g.a_pool = clsel::kPoolRhs; g.a_off = roff[f]; g.lda = fr.H;
+        g.b_pool = fr.fbuf; g.b_off = fr.off; g.ldb = fr.ld;
+        g.c_pool = clsel::kPoolRhs; g.c_off = xoff[f]; g.ldc = fr.H;
+      }
       g.alpha = 1.0; g.has_c0 = 0;
       gs.push_back(g);
     }
     if (!gd.empty())
-      S.bwd.push_back({kRhsGather, blob_push(S.blob, gd.data(), gd.size() * sizeof(gd[0])), (int)gd.size(), blk, 0});
+      S.bwd.push_back({kRhsGather, blob_push(S.blob, gd.data(), gd.size() * sizeof(gd[0])), (int)gd.size(), blk, tr});
     S.bwd.push_back(gemm_launch(S.blob, gs, 0, clsel::kTile64));
   }
   std::vector<clsel::SolScatterDesc> sd;
   int64_t blk = 0;
   for (size_t f = 0; f < nf; ++f) {
     const clsel::Front& fr = P.fronts[f];
-    sd.push_back({xoff[f], fr.site_off, blk, fr.p});
+    sd.push_back({xoff[f], fr.site_off, blk, fr.p, fr.H});
     blk += cdiv64((int64_t)fr.p * ns, 256);
   }
-  S.scatter = {kSolScatter, blob_push(S.blob, sd.data(), sd.size() * sizeof(sd[0])), (int)sd.size(), blk, 0};
+  S.scatter = {kSolScatter, blob_push(S.blob, sd.data(), sd.size() * sizeof(sd[0])), (int)sd.size(), blk, tr};
+  if (lowrank > 0 && !trans) {  // x -= (X C) T, T = rows j_k of x: [N][R] [R][ns]
+    std::vector<clsel::GemmDesc> g(1);
+    clsel::GemmDesc& d = g[0];
+    d.mode = 0; d.M = (int)P.N; d.N = ns; d.K = lowrank;
+    d.a_pool = clsel::kPoolWs; d.a_off = L.xc_off; d.lda = lowrank;
+    d.b_pool = clsel::kPoolRhs; d.b_off = S.t_off; d.ldb = ns;
+    d.c_pool = clsel::kPoolExt; d.c_off = 0; d.ldc = ns;
+    d.c0_pool = clsel::kPoolExt; d.c0_off = 0; d.ldc0 = ns;
+    d.alpha = -1.0; d.has_c0 = 1; d.kblock = 0;
+    S.corr = gemm_launch(S.blob, g, 0, clsel::kTile64);
+  }
 }
 
-// Host bounds check of every index the solve kernels and GEMMs can form.
-bool validate_solve_layout(const clsel::Plan& P, const SolveLayout& S, std::string& why) {
+// Host bounds check of every index the solve kernels and GEMMs can form. Element (row I,
+// right-hand side j) of a front block lies inside the block exactly when I < H and j < ns,
+// in either storage order, so the checks below are the same for right and left solves.
+bool validate_solve_layout(const clsel::Plan& P, const Layout& L, const SolveLayout& S, std::string& why) {
   const int ns = S.ns;
   const int64_t half = S.rhs_elems / 2, pool = P.pool_elems;
   auto bad = [&](const char* what) { why = what; return false; };
   auto desc = [&](const Launch& l) { return S.blob.data() + l.desc_off; };
+  std::vector<int64_t> block_H;  // H of the block starting at each roff (for child checks)
+  auto check_gemm = [&](const Launch& l) -> bool {
+    const clsel::GemmDesc* d = (const clsel::GemmDesc*)desc(l);
+    int64_t t = 0;
+    for (int i = 0; i < l.count; ++i) {
+      const clsel::GemmDesc& g = d[i];
+      if (g.mode != 0 || g.tile_start != t || g.kblock != 0) return bad("solve gemm table");
+      t += cdiv64(g.M, 64) * g.tiles_n;
+      auto lim = [&](int pid) -> int64_t {
+        if (pid == clsel::kPoolRhs) return S.stride;
+        if (pid == clsel::kPoolWs) return L.ws_elems;
+        if (pid == clsel::kPoolExt) return P.N * ns;
+        return pool;
+      };
+      if (g.a_off + (int64_t)(g.M - 1) * g.lda + g.K > lim(g.a_pool)) return bad("solve gemm A");
+      if (g.b_off + (int64_t)(g.K - 1) * g.ldb + g.N > lim(g.b_pool)) return bad("solve gemm B");
+      if (g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N > lim(g.c_pool)) return bad("solve gemm C");
+      if (g.has_c0 && g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N > lim(g.c0_pool)) return bad("solve gemm C0");
+    }
+    if (t != l.gridx) return bad("solve gemm grid");
+    return true;
+  };
   for (const std::vector<Launch>* ls : {&S.fwd, &S.bwd})
     for (const Launch& l : *ls) {
       if (l.kind == kRhsAsm) {
@@ -568,10 +697,10 @@ bool validate_solve_layout(const clsel::Plan& P, const SolveLayout& S, std::stri
           if ((int64_t)d[i].H * ns >= (int64_t(1) << 31)) return bad("rhs 32-bit index");
           for (int c = 0; c < d[i].nchild; ++c) {
             if (d[i].inv_off[c] + d[i].H > (int64_t)P.inv_maps.size()) return bad("rhs inverse map");
+            if (d[i].child_roff[c] + (int64_t)d[i].child_H[c] * ns > half) return bad("rhs child block");
             for (int r = 0; r < d[i].H; ++r) {
               const int ii = P.inv_maps[d[i].inv_off[c] + r];
-              if (ii >= 0 && d[i].child_roff[c] + (int64_t)(d[i].child_p[c] + ii + 1) * ns > half)
-                return bad("rhs child row");
+              if (ii >= 0 && d[i].child_p[c] + ii >= d[i].child_H[c]) return bad("rhs child row");
             }
           }
         }
@@ -585,24 +714,14 @@ bool validate_solve_layout(const clsel::Plan& P, const SolveLayout& S, std::stri
           if (d[i].rel_off + d[i].s > (int64_t)P.rel_maps.size()) return bad("rhs relative map");
           if (d[i].xoff + (int64_t)(d[i].p + d[i].s) * ns > 2 * half || d[i].roff + (int64_t)(d[i].p + d[i].s) * ns > half)
             return bad("rhs gather target");
+          if (d[i].par_xoff + (int64_t)d[i].par_H * ns > 2 * half) return bad("rhs gather source block");
           for (int r = 0; r < d[i].s; ++r)
-            if (d[i].par_xoff + (int64_t)(P.rel_maps[d[i].rel_off + r] + 1) * ns > 2 * half) return bad("rhs gather source");
+            if (P.rel_maps[d[i].rel_off + r] < 0 || P.rel_maps[d[i].rel_off + r] >= d[i].par_H)
+              return bad("rhs gather source");
         }
         if (blk != l.gridx) return bad("rhs gather grid");
       } else if (l.kind == kGemm) {
-        const clsel::GemmDesc* d = (const clsel::GemmDesc*)desc(l);
-        int64_t t = 0;
-        for (int i = 0; i < l.count; ++i) {
-          const clsel::GemmDesc& g = d[i];
-          if (g.mode != 0 || g.tile_start != t) return bad("solve gemm table");
-          t += cdiv64(g.M, 64) * g.tiles_n;
-          auto lim = [&](int pid) { return pid == clsel::kPoolRhs ? 2 * half : pool; };
-          if (g.a_off + (int64_t)(g.M - 1) * g.lda + g.K > lim(g.a_pool)) return bad("solve gemm A");
-          if (g.b_off + (int64_t)(g.K - 1) * g.ldb + g.N > lim(g.b_pool)) return bad("solve gemm B");
-          if (g.c_off + (int64_t)(g.M - 1) * g.ldc + g.N > lim(g.c_pool)) return bad("solve gemm C");
-          if (g.has_c0 && g.c0_off + (int64_t)(g.M - 1) * g.ldc0 + g.N > lim(g.c0_pool)) return bad("solve gemm C0");
-        }
-        if (t != l.gridx) return bad("solve gemm grid");
+        if (!check_gemm(l)) return false;
       } else {
         return bad("solve launch kind");
       }
@@ -612,11 +731,15 @@ bool validate_solve_layout(const clsel::Plan& P, const SolveLayout& S, std::stri
   for (int i = 0; i < S.scatter.count; ++i) {
     if (d[i].blk_start != blk) return bad("scatter block start");
     blk += cdiv64((int64_t)d[i].p * ns, 256);
-    if (d[i].xoff + (int64_t)d[i].p * ns > 2 * half) return bad("scatter source");
+    if (d[i].p > d[i].H || d[i].xoff + (int64_t)d[i].H * ns > 2 * half) return bad("scatter source");
     for (int r = 0; r < d[i].p / 3; ++r)
       if (P.front_sites[d[i].site_off + r] < 0 || P.front_sites[d[i].site_off + r] >= P.V) return bad("scatter site");
   }
   if (blk != S.scatter.gridx) return bad("scatter grid");
+  if (S.corr.gridx > 0) {
+    if (!check_gemm(S.corr)) return false;
+    if (S.t_off + (int64_t)L.R * ns > S.stride) return bad("solve correction rows");
+  }
   return true;
 }
 
@@ -642,6 +765,13 @@ struct cl_batch_s {
   SolveLayout solve;
   char* solve_blob = nullptr;
   double2* rhs = nullptr;
+  // the low-rank correction's right and left solves (R right-hand sides), their shared
+  // workspace, and the global index of every pivot column
+  SolveLayout smw_r, smw_l;
+  char* smw_blob_r = nullptr;
+  char* smw_blob_l = nullptr;
+  double2* smw_rhs = nullptr;
+  int32_t* d_pivglob = nullptr;
   double* params_host = nullptr;  // pinned staging
   int32_t* status = nullptr;
   char* dblob = nullptr;
@@ -715,7 +845,7 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
       case kPanel:
         clsel::launch_panel(l.rpt, grid, b->st, (const clsel::PanelDesc*)dp, b->fronts,
                             b->L.cfg_stride, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
-                            b->status);
+                            b->status, b->L.R > 0 ? P.opt.pivot_floor : 0.0);
         break;
       case kGemm: {
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -753,6 +883,9 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
   return 0;
 }
 
+int enqueue_smw(cl_batch b);
+clsel::SmwCtx smw_ctx(cl_batch b);
+
 int enqueue_factor(cl_batch b, const void* links_dev, bool capturing) {
   const clsel::Plan& P = b->plan->P;
   const int B = b->active;
@@ -768,7 +901,12 @@ int enqueue_factor(cl_batch b, const void* links_dev, bool capturing) {
   hipLaunchKernelGGL(clsel::k_link_inverse, dim3((unsigned)cdiv64(nl, 256)), dim3(256), 0, b->st,
                      b->links, b->linv, P.V * 4, B, b->status);
   HIPCHK(hipGetLastError());
-  return enqueue_launches(b, b->L.factor);
+  int rc = enqueue_launches(b, b->L.factor);
+  if (rc || b->L.R == 0) return rc;
+  // the perturbed pivots of each configuration, in pivot-column order (CL_ERANK past the cap)
+  hipLaunchKernelGGL(clsel::k_smw_list, dim3(B), dim3(256), 0, b->st, smw_ctx(b));
+  HIPCHK(hipGetLastError());
+  return 0;
 }
 
 int enqueue_selinv(cl_batch b) {
@@ -781,7 +919,7 @@ int enqueue_selinv(cl_batch b) {
                      b->st, b->fronts, b->L.cfg_stride, b->d_sel_off, b->d_sel_ld, P.V, B,
                      b->status, b->sel);
   HIPCHK(hipGetLastError());
-  return 0;
+  return enqueue_smw(b);
 }
 
 int enqueue_selected(cl_batch b, void* out) {
@@ -830,6 +968,7 @@ void free_batch(cl_batch b) {
   hipFree(b->sel); hipFree(b->params); hipFree(b->status); hipFree(b->dblob);
   hipFree(b->lparams); hipFree(b->kmax);
   hipFree(b->solve_blob); hipFree(b->rhs);
+  hipFree(b->smw_blob_r); hipFree(b->smw_blob_l); hipFree(b->smw_rhs); hipFree(b->d_pivglob);
   if (b->lparams_host) hipHostFree(b->lparams_host);
   if (b->ev_lparam) hipEventDestroy(b->ev_lparam);
   hipFree(b->d_front_sites); hipFree(b->d_site_coords); hipFree(b->d_inv); hipFree(b->d_rel); hipFree(b->d_sel_off);
@@ -857,6 +996,7 @@ const char* cl_strerror(int code) {
     case CL_ENONFINITE: return "non-finite or singular link";
     case CL_EHIP: return "HIP runtime error";
     case CL_ENODEV: return "no usable GPU";
+    case CL_ERANK: return "more perturbed pivots than the low-rank correction holds";
     default: return "unknown error";
   }
 }
@@ -872,6 +1012,8 @@ int cl_symbolic_ex(const int32_t dims[4], const cl_plan_opts* opts, cl_plan* out
     if (opts->nb > 0) o.nb = opts->nb;
     o.time_cuts = opts->time_cuts != 0;
     o.gemm_tile = opts->gemm_tile;
+    if (opts->lowrank_cap != 0) o.lowrank_cap = opts->lowrank_cap;
+    if (opts->pivot_floor != 0.0) o.pivot_floor = opts->pivot_floor;
   }
   if (o.gemm_tile != 0 && o.gemm_tile != clsel::kTile64 && o.gemm_tile != clsel::kTile128x64 &&
       o.gemm_tile != clsel::kTile128)
@@ -909,6 +1051,8 @@ int cl_plan_info(cl_plan plan, cl_plan_info_t* o) {
   o->flops_factor_alg = P.flops_factor_alg;
   o->flops_selinv_alg = P.flops_selinv_alg;
   o->flops_dense_inverse = P.flops_dense_inverse;
+  o->lowrank_cap = P.opt.lowrank_cap;
+  o->pivot_floor = P.opt.pivot_floor;
   return 0;
 }
 
@@ -1009,6 +1153,21 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
   TRY(upload(&b->d_rel, P.rel_maps));
   TRY(upload(&b->d_sel_off, P.sel_off));
   TRY(upload(&b->d_sel_ld, P.sel_ld));
+  if (b->L.R > 0) {  // the correction's right and left solves, R right-hand sides each
+    std::string why;
+    build_solve_layout(P, b->L, b->L.R, false, 0, b->smw_r);
+    build_solve_layout(P, b->L, b->L.R, true, 0, b->smw_l);
+    if (!validate_solve_layout(P, b->L, b->smw_r, why) || !validate_solve_layout(P, b->L, b->smw_l, why)) {
+      free_batch(b);
+      return fail(CL_EINVAL, "low-rank solve table check failed: " + why);
+    }
+    TRY(dalloc(&b->smw_blob_r, b->smw_r.blob.size()));
+    HTRY(hipMemcpy(b->smw_blob_r, b->smw_r.blob.data(), b->smw_r.blob.size(), hipMemcpyHostToDevice));
+    TRY(dalloc(&b->smw_blob_l, b->smw_l.blob.size()));
+    HTRY(hipMemcpy(b->smw_blob_l, b->smw_l.blob.data(), b->smw_l.blob.size(), hipMemcpyHostToDevice));
+    TRY(dalloc(&b->smw_rhs, (size_t)(b->smw_r.stride * B)));
+    TRY(upload(&b->d_pivglob, b->L.pivot_global));
+  }
   HTRY(hipMemset(b->status, 0, sizeof(int32_t) * B));
 #undef TRY
 #undef HTRY
@@ -1142,9 +1301,9 @@ int prepare_solve(cl_batch b, int ns) {
   if (b->solve.ns == ns && b->rhs) return 0;
   const clsel::Plan& P = b->plan->P;
   SolveLayout S;
-  build_solve_layout(P, ns, S);
+  build_solve_layout(P, b->L, ns, false, b->L.R, S);
   std::string why;
-  if (!validate_solve_layout(P, S, why)) return fail(CL_EINVAL, "solve table check failed: " + why);
+  if (!validate_solve_layout(P, b->L, S, why)) return fail(CL_EINVAL, "solve table check failed: " + why);
   HIPCHK(hipStreamSynchronize(b->st));  // the old workspace may still be in use
   hipFree(b->solve_blob); b->solve_blob = nullptr;
   hipFree(b->rhs); b->rhs = nullptr;
@@ -1152,38 +1311,51 @@ int prepare_solve(cl_batch b, int ns) {
   int rc;
   if ((rc = dalloc(&b->solve_blob, S.blob.size()))) return rc;
   HIPCHK(hipMemcpy(b->solve_blob, S.blob.data(), S.blob.size(), hipMemcpyHostToDevice));
-  if ((rc = dalloc(&b->rhs, (size_t)(S.rhs_elems * b->cap)))) return rc;
+  if ((rc = dalloc(&b->rhs, (size_t)(S.stride * b->cap)))) return rc;
   b->solve = std::move(S);
   return 0;
 }
 
-int enqueue_solve(cl_batch b, const void* rhs_dev, void* x_dev) {
+// Runs the launch tables of one solve: right-hand sides read from in (per-configuration
+// stride in_stride, layout [N][ns]), solution written (or added, accumulate) to out.
+int run_solve(cl_batch b, const SolveLayout& S, const char* dblob, double2* ws_rhs, const void* in,
+              int64_t in_stride, void* out, int64_t out_stride, int accumulate) {
   const clsel::Plan& P = b->plan->P;
-  const SolveLayout& S = b->solve;
   const int B = b->active, ns = S.ns;
-  const int64_t stride = S.rhs_elems, vstride = P.N * (int64_t)ns;
+  const int64_t stride = S.stride;
   auto run = [&](const Launch& l) -> int {
     if (l.gridx <= 0) return 0;
     const dim3 grid((unsigned)l.gridx, (unsigned)B);
-    const char* dp = b->solve_blob + l.desc_off;
+    const char* dp = dblob + l.desc_off;
     switch (l.kind) {
       case kRhsAsm:
-        hipLaunchKernelGGL(clsel::k_rhs_assemble, grid, dim3(256), 0, b->st, (const clsel::RhsAsmDesc*)dp,
-                           l.count, b->rhs, stride, (const double2*)rhs_dev, vstride, b->d_front_sites,
-                           b->d_inv, ns);
+        if (l.rpt)
+          hipLaunchKernelGGL(clsel::k_rhs_assemble<true>, grid, dim3(256), 0, b->st, (const clsel::RhsAsmDesc*)dp,
+                             l.count, ws_rhs, stride, (const double2*)in, in_stride, b->d_front_sites, b->d_inv, ns);
+        else
+          hipLaunchKernelGGL(clsel::k_rhs_assemble<false>, grid, dim3(256), 0, b->st, (const clsel::RhsAsmDesc*)dp,
+                             l.count, ws_rhs, stride, (const double2*)in, in_stride, b->d_front_sites, b->d_inv, ns);
         break;
       case kRhsGather:
-        hipLaunchKernelGGL(clsel::k_rhs_gather, grid, dim3(256), 0, b->st, (const clsel::RhsGatherDesc*)dp,
-                           l.count, b->rhs, stride, b->d_rel, ns);
+        if (l.rpt)
+          hipLaunchKernelGGL(clsel::k_rhs_gather<true>, grid, dim3(256), 0, b->st, (const clsel::RhsGatherDesc*)dp,
+                             l.count, ws_rhs, stride, b->d_rel, ns);
+        else
+          hipLaunchKernelGGL(clsel::k_rhs_gather<false>, grid, dim3(256), 0, b->st, (const clsel::RhsGatherDesc*)dp,
+                             l.count, ws_rhs, stride, b->d_rel, ns);
         break;
       case kSolScatter:
-        hipLaunchKernelGGL(clsel::k_sol_scatter, grid, dim3(256), 0, b->st, (const clsel::SolScatterDesc*)dp,
-                           l.count, b->rhs, stride, (double2*)x_dev, vstride, b->d_front_sites, ns);
+        if (l.rpt)
+          hipLaunchKernelGGL(clsel::k_sol_scatter<true>, grid, dim3(256), 0, b->st, (const clsel::SolScatterDesc*)dp,
+                             l.count, ws_rhs, stride, (double2*)out, out_stride, b->d_front_sites, ns, accumulate);
+        else
+          hipLaunchKernelGGL(clsel::k_sol_scatter<false>, grid, dim3(256), 0, b->st, (const clsel::SolScatterDesc*)dp,
+                             l.count, ws_rhs, stride, (double2*)out, out_stride, b->d_front_sites, ns, accumulate);
         break;
       default:
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
-                           b->rhs, stride, b->d_inv);
+                           ws_rhs, stride, b->d_inv, (double2*)out, out_stride);
     }
     HIPCHK(hipGetLastError());
     return 0;
@@ -1193,12 +1365,97 @@ int enqueue_solve(cl_batch b, const void* rhs_dev, void* x_dev) {
   for (const Launch& l : S.bwd) if ((rc = run(l))) return rc;
   return run(S.scatter);
 }
+
+clsel::SmwCtx smw_ctx(cl_batch b) {
+  const Layout& L = b->L;
+  clsel::SmwCtx c{};
+  c.ws = b->ws; c.ws_stride = L.ws_elems;
+  c.iws = b->iws; c.iws_stride = L.iws_elems;
+  c.pdelta_off = L.pdelta_off; c.x_off = L.x_off; c.y_off = L.y_off; c.xc_off = L.xc_off;
+  c.r_off = L.r_off; c.c_off = L.c_off; c.dl_off = L.dl_off;
+  c.peq_off = L.peq_off; c.li_off = L.li_off; c.lj_off = L.lj_off; c.cnt_off = L.cnt_off;
+  c.pivot_global = b->d_pivglob;
+  c.n = b->plan->P.N;
+  c.R = L.R;
+  c.status = b->status;
+  return c;
+}
+
+// The low-rank correction of the perturbed pivots, after the selected blocks of D~ are
+// gathered (see k_smw.hip): X and Y^T by right and left solves with one refinement step
+// each, C = (I + V^T X)^{-1}, X C, and the blocks corrected in place.
+int enqueue_smw(cl_batch b) {
+  const clsel::Plan& P = b->plan->P;
+  const Layout& L = b->L;
+  if (L.R == 0) return 0;
+  const int B = b->active;
+  const clsel::SmwCtx c = smw_ctx(b);
+  const dim3 g_nr((unsigned)cdiv64(P.N * L.R, 256), (unsigned)B);
+  const dim3 g_vr((unsigned)cdiv64(P.V * L.R, 256), (unsigned)B);
+  const dim3 g_rr((unsigned)cdiv64((int64_t)L.R * L.R, 256), (unsigned)B);
+  double2* rbuf = b->ws + L.r_off;
+  double2* X = b->ws + L.x_off;
+  double2* Yt = b->ws + L.y_off;
+  const int64_t wst = L.ws_elems;
+  int rc;
+  // X = D~^{-1} U, Y^T = D~^{-T} V
+  hipLaunchKernelGGL(clsel::k_smw_rhs, g_nr, dim3(256), 0, b->st, c, 0);
+  HIPCHK(hipGetLastError());
+  if ((rc = run_solve(b, b->smw_r, b->smw_blob_r, b->smw_rhs, rbuf, wst, X, wst, 0))) return rc;
+  hipLaunchKernelGGL(clsel::k_smw_rhs, g_nr, dim3(256), 0, b->st, c, 1);
+  HIPCHK(hipGetLastError());
+  if ((rc = run_solve(b, b->smw_l, b->smw_blob_l, b->smw_rhs, rbuf, wst, Yt, wst, 0))) return rc;
+  // one refinement step each: residual against D~ = D + perturbations, solve, add
+  for (int trans = 0; trans < 2; ++trans) {
+    hipLaunchKernelGGL(clsel::k_smw_residual, g_vr, dim3(256), 0, b->st, c, b->links, b->linv, b->params,
+                       b->params + b->cap, ldims(P), P.V, trans);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(clsel::k_smw_residual_delta, g_rr, dim3(256), 0, b->st, c, trans);
+    HIPCHK(hipGetLastError());
+    if ((rc = run_solve(b, trans ? b->smw_l : b->smw_r, trans ? b->smw_blob_l : b->smw_blob_r, b->smw_rhs,
+                        rbuf, wst, trans ? Yt : X, wst, 1)))
+      return rc;
+  }
+  hipLaunchKernelGGL(clsel::k_smw_capacitance, dim3(B), dim3(256), 0, b->st, c);
+  HIPCHK(hipGetLastError());
+  clsel::launch_gemm(0, L.smw_xc.tile, dim3((unsigned)L.smw_xc.gridx, (unsigned)B), b->st,
+                     (const clsel::GemmDesc*)(b->dblob + L.smw_xc.desc_off), L.smw_xc.count, b->fronts,
+                     L.cfg_stride, P.pool_elems, b->ws, L.ws_elems, b->iws, L.iws_elems, nullptr, 0, b->d_inv);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(clsel::k_smw_correct, dim3((unsigned)cdiv64(P.V * 81, 256), (unsigned)B), dim3(256), 0,
+                     b->st, c, b->sel, ldims(P), P.V);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
+
+int enqueue_solve(cl_batch b, const void* rhs_dev, void* x_dev) {
+  const clsel::Plan& P = b->plan->P;
+  const SolveLayout& S = b->solve;
+  const int64_t vstride = P.N * (int64_t)S.ns;
+  int rc;
+  if ((rc = run_solve(b, S, b->solve_blob, b->rhs, rhs_dev, vstride, x_dev, vstride, 0))) return rc;
+  if (b->L.R == 0) return 0;
+  // x -= X C (V^T x): the solution of D~ corrected to that of D
+  const clsel::SmwCtx c = smw_ctx(b);
+  const int B = b->active;
+  hipLaunchKernelGGL(clsel::k_smw_gather_rows, dim3((unsigned)cdiv64((int64_t)b->L.R * S.ns, 256), (unsigned)B),
+                     dim3(256), 0, b->st, c, (const double2*)x_dev, vstride, b->rhs + S.t_off, S.stride, S.ns);
+  HIPCHK(hipGetLastError());
+  clsel::launch_gemm(0, S.corr.tile, dim3((unsigned)S.corr.gridx, (unsigned)B), b->st,
+                     (const clsel::GemmDesc*)(b->solve_blob + S.corr.desc_off), S.corr.count, b->fronts,
+                     b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems, b->rhs,
+                     S.stride, b->d_inv, (double2*)x_dev, vstride);
+  HIPCHK(hipGetLastError());
+  return 0;
+}
 }  // namespace
 
 int cl_solve(cl_batch b, const void* rhs_dev, int32_t ns, void* x_dev) {
   if (!b || !rhs_dev || !x_dev) return fail(CL_EINVAL, "null argument");
   if (ns < 1 || ns > kMaxRhs) return fail(CL_EINVAL, "right-hand sides must be 1 .. 4096");
   if (b->state < 1) return fail(CL_EORDER, "cl_solve before cl_factor");
+  if (b->L.R > 0 && b->state < 2)
+    return fail(CL_EORDER, "cl_solve before cl_selinv (the perturbed pivots' correction comes from it)");
   int rc;
   HIPCHK(hipSetDevice(b->device));
   if ((rc = prepare_solve(b, ns))) return rc;
@@ -1331,6 +1588,19 @@ int cl_status(cl_batch b, int32_t* out) {
   HIPCHK(hipSetDevice(b->device));
   HIPCHK(hipStreamSynchronize(b->st));
   HIPCHK(hipMemcpy(out, b->status, sizeof(int32_t) * b->active, hipMemcpyDeviceToHost));
+  return 0;
+}
+
+int cl_batch_perturbations(cl_batch b, int32_t* out) {
+  if (!b || !out) return fail(CL_EINVAL, "null argument");
+  HIPCHK(hipSetDevice(b->device));
+  HIPCHK(hipStreamSynchronize(b->st));
+  for (int i = 0; i < b->active; ++i) {
+    out[i] = 0;
+    if (b->L.R > 0)
+      HIPCHK(hipMemcpy(out + i, b->iws + (int64_t)i * b->L.iws_elems + b->L.cnt_off + 1, sizeof(int32_t),
+                       hipMemcpyDeviceToHost));
+  }
   return 0;
 }
 

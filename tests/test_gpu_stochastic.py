@@ -36,6 +36,7 @@ def test_solve_matches_dense(torch, dims, ns):
     b = clsel.Batch(plan, 2)
     lt = torch.from_numpy(links).to("cuda")
     b.factor(lt, M, MU)
+    b.selinv()  # the correction of perturbed pivots comes from the selected inversion
     x = b.solve(torch.from_numpy(rhs).to("cuda")).cpu().numpy()
     assert (b.status() == 0).all()
     b.close()
@@ -82,6 +83,7 @@ def test_stochastic_drift_matches_oracle(torch):
     plan = clsel.Plan(dims)
     b = clsel.Batch(plan, 1)
     b.factor(torch.from_numpy(links[None].copy()).to("cuda"), M, MU)
+    b.selinv()
     xit = torch.from_numpy(xi[None].copy()).to("cuda")
     x = b.solve(xit)
     est = b.stochastic_blocks(xit, x)
@@ -96,16 +98,36 @@ def test_stochastic_drift_matches_oracle(torch):
 
 
 def test_solve_unchanged_by_selected_inversion(torch):
-    """The selected inversion writes its fronts beside the factors, so a solve after it
-    gives the same bits as a solve right after the factorisation."""
+    """Without pivot perturbation the selected inversion writes its fronts beside the
+    factors, so a solve after it gives the same bits as a solve right after the
+    factorisation."""
     dims = (4, 4, 4, 4)
     lt = torch.from_numpy(gen_links(dims, 9, 0.1)[None].copy()).to("cuda")
     rhs = torch.from_numpy(gen_sources(dims, 5, 4)[None].copy()).to("cuda")
-    plan = clsel.Plan(dims)
+    plan = clsel.Plan(dims, pivot_floor=-1.0)
     b = clsel.Batch(plan, 1)
     b.factor(lt, M, MU)
     x1 = b.solve(rhs).cpu().numpy()
     b.selinv()
+    x2 = b.solve(rhs).cpu().numpy()
+    b.close()
+    assert np.array_equal(x1, x2)
+
+
+def test_solve_with_perturbed_pivots_needs_the_selected_inversion(torch):
+    """With pivot perturbation the solve's correction to D (from D~) comes from the
+    selected inversion: a solve right after the factorisation is a call-order error, and
+    repeated solves after it give the same bits."""
+    dims = (4, 4, 4, 4)
+    lt = torch.from_numpy(gen_links(dims, 9, 0.1)[None].copy()).to("cuda")
+    rhs = torch.from_numpy(gen_sources(dims, 5, 4)[None].copy()).to("cuda")
+    b = clsel.Batch(clsel.Plan(dims), 1)
+    b.factor(lt, M, MU)
+    with pytest.raises(clsel.ClselError) as e:
+        b.solve(rhs)
+    assert e.value.code == clsel.CL_EORDER
+    b.selinv()
+    x1 = b.solve(rhs).cpu().numpy()
     x2 = b.solve(rhs).cpu().numpy()
     b.close()
     assert np.array_equal(x1, x2)
