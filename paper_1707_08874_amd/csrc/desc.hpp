@@ -73,8 +73,10 @@ struct GemmDesc {
   int child_p[4], child_ld[4];
   int64_t inv_off[4];     // per child: front row -> child update row (-1: none)
   int64_t child_off[4];   // child front offset, including its pool
-  // modes 1, 2
+  // modes 1, 2 (mode 2: B = Rt with leading dimension ldb; output row r is front row
+  // row_base + r, so one step can also sweep the update rows' pivot columns)
   int k, nbk, p, ld, last;
+  int row_base;
   int64_t x_off, y_off;   // input / output front (incl. pool)
   int64_t rt_off;         // ws: nbk x H transformed pivot rows (ld = H)
   int64_t pinv_off;       // ws

@@ -22,7 +22,9 @@
 //
 // Modes (see desc.hpp): 0 plain grouped GEMM for the selected-inverse products,
 // 1 transformed pivot rows of a Gauss-Jordan block step, 2 the front update of
-// that step, written to the other pool with the step's row permutation applied.
+// that step, written to the other pool with the step's row permutation applied (rows
+// from row_base on: the pivot rows, or the update rows' pivot columns, which the
+// sweep turns into -L^ by elimination).
 // Work-group ids are remapped so that each of the 8 XCDs (separate L2 caches) gets a
 // contiguous range of tiles, which share operand rows and columns.
 #include <type_traits>
@@ -73,7 +75,7 @@ __device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE, 
   const double2 z = make_double2(0.0, 0.0);
   if (t >= d.K || o.ai[r] >= d.M) return z;
   if (MODE == 2) {
-    const int i = o.ai[r];
+    const int i = o.ai[r] + d.row_base;
     if (i >= d.k && i < d.k + d.nbk) return make_double2(i - d.k == t ? -1.0 : 0.0, 0.0);
   }
   return o.arow[r][t];
@@ -85,7 +87,10 @@ __device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned G) {
   return x * q + min(x, r) + local;
 }
 
-template <int MODE, int TM, int TN, int BK, int NBUF>
+// SOLVE: the same kernel for the products of the multi-right-hand-side solves (one side
+// narrow, one chain of products per output), instantiated apart so that profiles tell
+// the two kinds of launch apart.
+template <int MODE, int TM, int TN, int BK, int NBUF, bool SOLVE = false>
 __global__ void __launch_bounds__(kGemmThreads, (TM * TN > 4) ? 1 : 4)
 k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   constexpr int BM = 32 * TM, BN = 32 * TN;
@@ -132,7 +137,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     if (i < d.M) {
       if (MODE == 0) o.arow[r] = pool_ptr(g, b, d.a_pool) + d.a_off + (int64_t)i * d.lda;
       else if (MODE == 1) o.arow[r] = W + d.pinv_off + (int64_t)i * d.nbk;
-      else o.arow[r] = F + d.x_off + (int64_t)IW[d.rmap_off + i] * d.ld + d.k;
+      else o.arow[r] = F + d.x_off + (int64_t)IW[d.rmap_off + d.row_base + i] * d.ld + d.k;
     }
   }
   const int bcol = col0 + b_n;
@@ -149,7 +154,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       if (j >= d.k && j < d.k + d.nbk) return make_double2(j - d.k == t ? 1.0 : 0.0, 0.0);
       return o.bbase[(int64_t)IW[d.piv_off + t] * d.ld + j];
     }
-    return o.bbase[(int64_t)t * d.N + j];
+    return o.bbase[(int64_t)t * d.ldb + j];
   };
 
   d4 cr[TM][TN], ci[TM][TN];
@@ -299,7 +304,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   static_assert(kKChunk % BK == 0, "chunk of whole stages");
   // (the 128 x 128 tile keeps one chain: its accumulators leave no registers for the
   // partial sums, which would spill)
-  constexpr bool kChunkable = MODE == 0 && TM * TN <= 8;
+  constexpr bool kChunkable = MODE == 0 && TM * TN <= 8 && !SOLVE;
   // at most kMaxChunks chunks: a longer K gets longer chunks, which bounds the round trips
   // of the running totals (for K <= kMaxChunks * kKChunk the chunk is kKChunk)
   const int chunk_stages = max(kStagesPerChunk, (nst + kMaxChunks - 1) / kMaxChunks);
@@ -387,8 +392,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + wm * (BM / 2) + i * 16 + 4 * r + l4;
-        const bool rok = row < d.M && !(row >= d.k && row < d.k + d.nbk);
-        const double2* xr = rok ? F + d.x_off + (int64_t)IW[d.rmap_off + row] * d.ld : nullptr;
+        const int frow = d.row_base + row;  // row of the front
+        const bool rok = row < d.M && !(frow >= d.k && frow < d.k + d.nbk);
+        const double2* xr = rok ? F + d.x_off + (int64_t)IW[d.rmap_off + frow] * d.ld : nullptr;
 #pragma unroll
         for (int j = 0; j < TN; ++j) {
           const int col = col0 + wn * (BN / 2) + j * 16 + l16;
@@ -433,7 +439,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
           // Y = base - A*Rt, base = X[rmap(row)][col] off the pivot rows and panel columns
           int oc = col;
           if (d.last && col < d.p) oc = IW[d.rowid_off + col];
-          F[d.y_off + (int64_t)row * d.ld + oc] = csub(bs[j][r], acc);
+          F[d.y_off + (int64_t)(d.row_base + row) * d.ld + oc] = csub(bs[j][r], acc);
         }
       }
   }
@@ -442,11 +448,13 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* descs, int ndesc,
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
-                 int64_t rhs_stride, const int32_t* inv_maps, double2* ext, int64_t ext_stride) {
+                 int64_t rhs_stride, const int32_t* inv_maps, double2* ext, int64_t ext_stride,
+                 bool solve) {
   GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride, rhs, rhs_stride, inv_maps,
             ext, ext_stride};
   const dim3 blk(kGemmThreads);
-  if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
+  if (solve) hipLaunchKernelGGL((k_gemm<0, 2, 2, 8, 2, true>), grid, blk, 0, st, descs, ndesc, g);
+  else if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
   else if (mode == 0 && tile == kTile128x64) hipLaunchKernelGGL((k_gemm<0, 4, 2, 16, 1>), grid, blk, 0, st, descs, ndesc, g);
   else if (mode == 0) hipLaunchKernelGGL((k_gemm<0, 2, 2, 8, 2>), grid, blk, 0, st, descs, ndesc, g);
   else if (mode == 1) hipLaunchKernelGGL((k_gemm<1, 2, 2, 8, 2>), grid, blk, 0, st, descs, ndesc, g);

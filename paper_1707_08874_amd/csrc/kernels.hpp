@@ -82,6 +82,6 @@ void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* 
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
                  int64_t rhs_stride, const int32_t* inv_maps, double2* ext = nullptr,
-                 int64_t ext_stride = 0);
+                 int64_t ext_stride = 0, bool solve = false);
 
 }  // namespace clsel

@@ -106,6 +106,11 @@ Launch gemm_launch(std::vector<char>& blob, std::vector<clsel::GemmDesc>& g, int
   return l;
 }
 
+// Whether the sweep eliminates a front's update rows over its pivot columns (their
+// intermediate values need p <= s columns of the unused S x S blocks); otherwise
+// -L^ = -A_SJ A_JJ^{-1} is an explicit product after the sweep.
+inline bool sweeps_lhat(const clsel::Front& f) { return f.s > 0 && f.p <= f.s; }
+
 void build_layout(const clsel::Plan& P, Layout& L) {
   const int64_t pool = P.pool_elems;
   const int nb = P.opt.nb;
@@ -209,13 +214,28 @@ void build_layout(const clsel::Plan& P, Layout& L) {
         a.rt_off = rt_off; a.pinv_off = p.pinv_off; a.piv_off = p.piv_off;
         a.rmap_off = p.rmap_off; a.rowid_off = p.rowid_off;
         g1.push_back(a);
-        // only the pivot rows are swept; the update rows are finished after the sweep
+        // the pivot rows are swept over every column; the update rows only over the pivot
+        // columns, which the sweep turns into -L^ = -A_SJ A_JJ^{-1} by elimination (as
+        // accurate as a solve; an explicit product with A_JJ^{-1} is not). Their
+        // Schur complement is a long-K GEMM after the sweep.
         clsel::GemmDesc u = a;
-        u.mode = 2; u.M = fr.p; u.N = fr.H; u.K = nbk;
+        u.mode = 2; u.M = fr.p; u.N = fr.H; u.K = nbk; u.ldb = fr.H; u.row_base = 0;
         u.tiles_n = (int)cdiv64(fr.H, 64);
         u.tile_start = t2; t2 += cdiv64(fr.p, 64) * u.tiles_n;
         u.last = (q == fr.nsteps - 1) ? 1 : 0;
         g2.push_back(u);
+        if (sweeps_lhat(fr)) {
+          // A_SJ (pool 0) -> ... -> -L^ (pool 1), ping-ponging through the first p columns
+          // of the S x S blocks of pool 0 and pool 1, which hold nothing during the sweep
+          auto qbuf = [&](int j) { return (int64_t)(j % 2) * pool + fr.off + fr.p; };
+          clsel::GemmDesc w = u;
+          w.M = fr.s; w.N = fr.p; w.row_base = fr.p;
+          w.x_off = q == 0 ? fr.off : qbuf(q - 1);
+          w.y_off = q == fr.nsteps - 1 ? pool + fr.off : qbuf(q);
+          w.tiles_n = (int)cdiv64(fr.p, 64);
+          w.tile_start = t2; t2 += cdiv64(fr.s, 64) * w.tiles_n;
+          g2.push_back(w);
+        }
       }
       ws_max = std::max(ws_max, wso);
       iws_max = std::max(iws_max, iwo);
@@ -252,6 +272,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
       ss.tiles_n = (int)cdiv64(ss.N, 64);
       ss.tile_start = ts; ts += cdiv64(ss.M, 64) * ss.tiles_n;
       gs.push_back(ss);
+      if (sweeps_lhat(fr)) continue;  // -L^ came out of the sweep
       clsel::GemmDesc sj{};
       sj.mode = 0; sj.M = fr.s; sj.N = fr.p; sj.K = fr.p;
       sj.a_pool = 0; sj.a_off = o + p * ld; sj.lda = (int)ld;
@@ -454,13 +475,23 @@ bool validate_layout(const clsel::Plan& P, const Layout& L, std::string& why) {
             }
           }
         } else {
-          const int H = g.N;  // both modes span every column of the front
-          REQ(g.x_off + (int64_t)H * g.ld <= two && g.y_off + (int64_t)H * g.ld <= two, "gemm front", g.x_off, two);
+          // H: the front's rows (mode 1 spans every column; mode 2 reads Rt with ld H)
+          const int H = g.mode == 1 ? g.N : g.ldb;
+          REQ(g.x_off + (int64_t)H * g.ld <= two && g.y_off >= 0 && g.x_off >= 0, "gemm front", g.x_off, two);
           REQ(g.rt_off + (int64_t)g.nbk * H <= L.ws_elems, "gemm Rt", g.rt_off, L.ws_elems);
           REQ(g.pinv_off + (int64_t)g.nbk * g.nbk <= L.ws_elems, "gemm pinv", g.pinv_off, L.ws_elems);
           REQ(g.piv_off + g.nbk <= L.iws_elems && g.rmap_off + H <= L.iws_elems, "gemm maps", g.rmap_off, L.iws_elems);
           REQ(g.K == g.nbk && g.k + g.nbk <= g.p && g.p <= H, "gemm step", g.k, g.p);
-          REQ(g.mode == 1 ? g.M == g.nbk : g.M == g.p, "gemm rows", g.M, g.p);
+          if (g.mode == 1) {
+            REQ(g.M == g.nbk, "gemm rows", g.M, g.nbk);
+          } else {
+            // the pivot rows over all H columns, or the update rows over the p pivot columns
+            const bool pivots = g.row_base == 0 && g.M == g.p && g.N == H;
+            const bool updates = g.row_base == g.p && g.row_base + g.M == H && g.N == g.p && g.p <= g.M;
+            REQ(pivots || updates, "gemm mode-2 rows", g.row_base, g.M);
+            const int64_t last = (int64_t)(g.row_base + g.M - 1) * g.ld + g.N;
+            REQ(g.x_off + last <= two && g.y_off + last <= two, "gemm mode-2 block", g.y_off, two);
+          }
         }
       }
       REQ(t == l.gridx, "gemm grid", t, l.gridx);
@@ -1355,7 +1386,7 @@ int run_solve(cl_batch b, const SolveLayout& S, const char* dblob, double2* ws_r
       default:
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
-                           ws_rhs, stride, b->d_inv, (double2*)out, out_stride);
+                           ws_rhs, stride, b->d_inv, (double2*)out, out_stride, true);
     }
     HIPCHK(hipGetLastError());
     return 0;
@@ -1420,7 +1451,8 @@ int enqueue_smw(cl_batch b) {
   HIPCHK(hipGetLastError());
   clsel::launch_gemm(0, L.smw_xc.tile, dim3((unsigned)L.smw_xc.gridx, (unsigned)B), b->st,
                      (const clsel::GemmDesc*)(b->dblob + L.smw_xc.desc_off), L.smw_xc.count, b->fronts,
-                     L.cfg_stride, P.pool_elems, b->ws, L.ws_elems, b->iws, L.iws_elems, nullptr, 0, b->d_inv);
+                     L.cfg_stride, P.pool_elems, b->ws, L.ws_elems, b->iws, L.iws_elems, nullptr, 0, b->d_inv,
+                     nullptr, 0, true);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(clsel::k_smw_correct, dim3((unsigned)cdiv64(P.V * 81, 256), (unsigned)B), dim3(256), 0,
                      b->st, c, b->sel, ldims(P), P.V);
@@ -1444,7 +1476,7 @@ int enqueue_solve(cl_batch b, const void* rhs_dev, void* x_dev) {
   clsel::launch_gemm(0, S.corr.tile, dim3((unsigned)S.corr.gridx, (unsigned)B), b->st,
                      (const clsel::GemmDesc*)(b->solve_blob + S.corr.desc_off), S.corr.count, b->fronts,
                      b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems, b->rhs,
-                     S.stride, b->d_inv, (double2*)x_dev, vstride);
+                     S.stride, b->d_inv, (double2*)x_dev, vstride, true);
   HIPCHK(hipGetLastError());
   return 0;
 }

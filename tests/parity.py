@@ -2,19 +2,18 @@
 
 Blocks: relative Frobenius error of every 3x3 selected block,
     ||Z_b - Z_b^ref||_F / ||Z_b^ref||_F  <= 1e-10.
-Drift: the absolute error of K_{a,x,nu} comes from the rounding of the two blocks P,
-Q of its link (Eq. 8), so it is measured against the size of that link's drift:
+Drift: relative error of each link's drift vector (its eight components),
     max_a |K_{a,x,nu} - K^ref_{a,x,nu}| / max_a |K^ref_{a,x,nu}|  <= 1e-10.
-A purely component-wise ratio is ill-conditioned for components far below their
-link's scale (the dense LAPACK oracle itself is only accurate to ~kappa(D)*eps
-in absolute terms), so it is reported but not gated.
+A component's absolute error is set by the rounding of the two blocks P, Q of its link
+(Eq. 8), so a component far below its link's scale cannot be accurate to 1e-10 of itself
+in double precision: against blocks from a long-double selected inversion of the same
+matrix, the dense LAPACK oracle's own component-wise error (with a floor of 1e-6 max|K|)
+is 6e-10 to 1e-9 on 8^3x4 configurations, while its per-link error is 1e-11 to 2e-11.
+The component-wise ratio is therefore reported (drift_componentwise) but not gated.
 
-Conditioning: selected inversion with a static (nested-dissection) elimination
-order pivots only inside each supernode, so the Schur complements it forms can be
-worse conditioned than D itself; its forward error grows like kappa(D) * u. The
-gate is therefore tol(kappa) = max(1e-10, 1e-14 * kappa_1(D)): exactly 1e-10 for
-kappa_1(D) <= 1e4 and proportional to the conditioning beyond (1e-14 * kappa is
-about 90 * kappa * u).
+The conditioning-scaled tolerance max(1e-10, 1e-14 kappa_1(D)) is kept only for paths
+whose accuracy is held as a regression floor (the selected inversion without pivot
+perturbation).
 """
 import numpy as np
 

@@ -11,7 +11,7 @@ import pytest
 import oracle
 from paper_1707_08874_amd import clsel
 from paper_1707_08874_amd.inputs import gen_links, gen_batch, unit_links, pure_gauge_links, eps_for_seed
-from parity import assert_parity, block_errors, drift_errors, kappa1, tolerance
+from parity import TOL, assert_parity, block_errors, drift_errors, kappa1, tolerance
 from free_field import free_blocks, pure_gauge_blocks
 
 pytestmark = pytest.mark.gpu
@@ -72,7 +72,7 @@ def test_single_config_matches_oracle(torch_cuda, dims, kw):
     sel, drift, st = _run(torch_cuda, dims, U[None], M, MU, **kw)
     assert st.tolist() == [0]
     ref_sel, ref_drift, tol = _oracle(U, dims, M, MU)
-    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, tol, label=str(dims))
+    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, TOL, label=str(dims))
     print(f"[gpu] worst block {be:.2e} drift {de:.2e} tol {tol:.1e}", flush=True)
 
 
@@ -83,7 +83,7 @@ def test_8x8x8x4_plain_matches_oracle(torch_cuda):
     sel, drift, st = _run(torch_cuda, dims, U[None], M, MU)
     assert st.tolist() == [0]
     ref_sel, ref_drift, tol = _oracle(U, dims, M, MU)
-    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, tol, label="8^3x4")
+    be, de = assert_parity(sel[0], drift[0], ref_sel, ref_drift, TOL, label="8^3x4")
     print(f"[gpu] 8^3x4 worst block {be:.2e} drift {de:.2e} tol {tol:.1e}", flush=True)
 
 
@@ -99,7 +99,7 @@ def test_batch_per_config_parameters(torch_cuda):
     assert st.tolist() == [0, 0, 0, 0]
     for b in range(4):
         ref_sel, ref_drift, tol = _oracle(U[b], dims, m[b], mu[b])
-        assert_parity(sel[b], drift[b], ref_sel, ref_drift, tol, label=f"member {b}")
+        assert_parity(sel[b], drift[b], ref_sel, ref_drift, TOL, label=f"member {b}")
     s1, d1, _ = _run(torch_cuda, dims, U[2:3], m[2:3], mu[2:3])
     assert np.array_equal(s1[0], sel[2]) and np.array_equal(d1[0], drift[2])
 
@@ -152,7 +152,7 @@ def test_nonfinite_link_is_isolated(torch_cuda):
     assert st[0] == 0 and st[1] == clsel.CL_ENONFINITE
     assert np.all(np.isnan(sel[1]))
     ref_sel, ref_drift, tol = _oracle(U[0], dims, M, MU)
-    assert_parity(sel[0], drift[0], ref_sel, ref_drift, tol)
+    assert_parity(sel[0], drift[0], ref_sel, ref_drift, TOL)
 
 
 def test_call_order_errors(torch_cuda):

@@ -5,7 +5,7 @@ import pytest
 import oracle
 from paper_1707_08874_amd import clsel
 from paper_1707_08874_amd.serve import Server, make_requests
-from parity import assert_parity, kappa1, tolerance
+from parity import TOL, assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +46,7 @@ def test_mixed_stream_equals_alone(torch_cuda):
         Z = oracle.inverse_dense(D)
         ref = oracle.selected_blocks(Z, r.dims)
         assert_parity(r.selected, r.drift, ref, oracle.drift_from_blocks(ref, r.links, r.dims, r.mu),
-                      tolerance(kappa1(D, Z)))
+                      TOL)
 
 
 def test_budget_forces_queueing_and_eviction(torch_cuda):
