@@ -198,6 +198,23 @@ int cl_drift_from_blocks(cl_batch batch, const void* blocks_dev, void* out_dev);
  * HIP graph when enabled. Either output pointer may be NULL. */
 int cl_run(cl_batch batch, const void* links_dev, const double* m_host, const double* mu_host,
            void* selected_out_dev, void* drift_out_dev);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): the work of cl_run (factorisation,
+ * selected inversion with the low-rank correction, selected blocks, drift) for `batch`
+ * configurations of `plan`, with every workspace and table in one static device array of
+ * CL_NOALLOC_BYTES bytes per GPU instead of a batch. No device memory is allocated or
+ * freed. links_dev, m_host, mu_host, selected_out_dev and drift_out_dev are as for
+ * cl_factor and cl_run (either output may be NULL); status_host receives `batch` statuses
+ * as cl_status gives them. The work runs on hip_stream (NULL: the null stream) and the
+ * call returns after it has finished. A plan and batch whose workspace exceeds the array
+ * is refused with CL_EINVAL (cl_last_error gives the bytes needed; 4^4 needs about 37 MiB
+ * per configuration). The array is shared by every call on one GPU and keeps the last
+ * call's contents: calls that overlap on one GPU (other threads, other streams) race and
+ * must be serialised by the caller. */
+#define CL_NOALLOC_BYTES (128u << 20)
+int cl_run_noalloc(cl_plan plan, int32_t batch, const void* links_dev, const double* m_host,
+                   const double* mu_host, void* selected_out_dev, void* drift_out_dev,
+                   int32_t* status_host, void* hip_stream);
 /* Waits for the batch's work and copies one status per active configuration:
  * 0, CL_ESINGULAR, CL_ENONFINITE or CL_ERANK. Returns 0 or an API error. */
 int cl_status(cl_batch batch, int32_t* per_config_host);

@@ -53,7 +53,7 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
            "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables",
            "cl_gauge_drift", "cl_langevin_update", "cl_solve", "cl_stochastic_blocks",
-           "cl_drift_from_blocks", "cl_batch_perturbations"]
+           "cl_drift_from_blocks", "cl_batch_perturbations", "cl_run_noalloc"]
 
 
 def lib():
@@ -98,6 +98,7 @@ def lib():
         "cl_stochastic_blocks": (ctypes.c_int, [vp, vp, vp, ctypes.c_int32, vp]),
         "cl_drift_from_blocks": (ctypes.c_int, [vp, vp, vp]),
         "cl_batch_perturbations": (ctypes.c_int, [vp, i32p]),
+        "cl_run_noalloc": (ctypes.c_int, [vp, ctypes.c_int32, vp, dp, dp, vp, vp, i32p, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -160,6 +161,30 @@ class Plan:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.cl_plan_destroy(self._h)
             self._h = None
+
+
+def run_noalloc(plan: "Plan", links, m, mu, selected_out=None, drift_out=None, stream=None):
+    """cl_run_noalloc: the whole path for links [B][V][4][3][3] (complex128 GPU tensor) with
+    every workspace in the library's static device array; no device memory is allocated by
+    the library. Outputs are the caller's tensors (allocated here when not given, by torch).
+    Returns (selected, drift, status) after the work has finished."""
+    import torch
+    B, V = int(links.shape[0]), int(plan.info()["volume"])
+    if tuple(links.shape[1:]) != (V, 4, 3, 3):
+        raise ClselError(CL_EINVAL, f"links must be [B][{V}][4][3][3]")
+    if selected_out is None:
+        selected_out = torch.empty((B, V, 9, 3, 3), dtype=torch.complex128, device=links.device)
+    if drift_out is None:
+        drift_out = torch.empty((B, V, 4, 8), dtype=torch.complex128, device=links.device)
+    m = np.ascontiguousarray(np.broadcast_to(np.asarray(m, dtype=np.float64), (B,)))
+    mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, dtype=np.float64), (B,)))
+    status = np.zeros(B, dtype=np.int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().cl_run_noalloc(plan._h, B, _dev_ptr(links), m.ctypes.data_as(dp), mu.ctypes.data_as(dp),
+                                _dev_ptr(selected_out), _dev_ptr(drift_out),
+                                status.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                _stream_handle(stream)))
+    return selected_out, drift_out, status
 
 
 def _stream_handle(stream):

@@ -1525,6 +1525,135 @@ int cl_drift_from_blocks(cl_batch b, const void* blocks_dev, void* out) {
   return end(b);
 }
 
+}  // extern "C"
+
+// ------------------------------------------------------------ no-allocation entry point
+// The workspaces of cl_run_noalloc live in this array. Host code never passes its name to
+// a kernel or a copy (on the host the name is only a stand-in): it takes the device
+// address with hipGetSymbolAddress, once per device with that device current, and uses
+// that address everywhere.
+static __device__ __align__(256) unsigned char scratch[CL_NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+int scratch_address(int device, char** out) {
+  if (device < 0 || device >= 64) return fail(CL_ENODEV, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(CL_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = (char*)g_scratch_ptr[device];
+  return 0;
+}
+
+// Carves 256-byte aligned pieces out of the scratch array.
+struct Carver {
+  char* base;
+  size_t used = 0;
+  template <class T>
+  T* take(size_t n) {
+    used = (used + 255) & ~size_t(255);
+    T* p = (T*)(base + used);
+    used += (n ? n : 1) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int cl_run_noalloc(cl_plan plan, int32_t batch, const void* links_dev, const double* m_host,
+                   const double* mu_host, void* sel_out, void* drift_out, int32_t* status_host,
+                   void* hip_stream) {
+  if (!plan || !links_dev || !m_host || !mu_host || !status_host || batch < 1 || batch > 65535)
+    return fail(CL_EINVAL, "null argument or batch out of range");
+  const clsel::Plan& P = plan->P;
+  int device = 0;
+  HIPCHK(hipGetDevice(&device));
+  // the same tables and launch lists a batch builds, on the host
+  cl_batch_s b;
+  b.plan = plan;
+  b.cap = b.active = batch;
+  b.device = device;
+  b.st = b.user = (hipStream_t)hip_stream;
+  build_layout(P, b.L);
+  std::string why;
+  if (!validate_layout(P, b.L, why)) return fail(CL_EINVAL, "launch table check failed: " + why);
+  if (b.L.R > 0) {
+    build_solve_layout(P, b.L, b.L.R, false, 0, b.smw_r);
+    build_solve_layout(P, b.L, b.L.R, true, 0, b.smw_l);
+    if (!validate_solve_layout(P, b.L, b.smw_r, why) || !validate_solve_layout(P, b.L, b.smw_l, why))
+      return fail(CL_EINVAL, "low-rank solve table check failed: " + why);
+  }
+  char* base = nullptr;
+  int rc;
+  if ((rc = scratch_address(device, &base))) return rc;
+  const int64_t B = batch;
+  Carver c{base};
+  b.dblob = c.take<char>(b.L.blob.size());
+  b.d_front_sites = c.take<int32_t>(P.front_sites.size());
+  b.d_site_coords = c.take<int32_t>(P.site_coords.size());
+  b.d_inv = c.take<int32_t>(P.inv_maps.size());
+  b.d_rel = c.take<int32_t>(P.rel_maps.size());
+  b.d_sel_off = c.take<int64_t>(P.sel_off.size());
+  b.d_sel_ld = c.take<int32_t>(P.sel_ld.size());
+  b.params = c.take<double>(2 * B);
+  b.status = c.take<int32_t>(B);
+  b.fronts = c.take<double2>(B * b.L.cfg_stride);
+  b.ws = c.take<double2>(B * b.L.ws_elems);
+  b.iws = c.take<int32_t>(B * b.L.iws_elems);
+  b.links = c.take<double2>(B * b.L.links_elems);
+  b.linv = c.take<double2>(B * b.L.links_elems);
+  b.sel = c.take<double2>(B * b.L.sel_elems);
+  if (b.L.R > 0) {
+    b.smw_blob_r = c.take<char>(b.smw_r.blob.size());
+    b.smw_blob_l = c.take<char>(b.smw_l.blob.size());
+    b.smw_rhs = c.take<double2>(B * b.smw_r.stride);
+    b.d_pivglob = c.take<int32_t>(b.L.pivot_global.size());
+  }
+  if (c.used > (size_t)CL_NOALLOC_BYTES)
+    return fail(CL_EINVAL, "cl_run_noalloc: this plan and batch need " + std::to_string(c.used) +
+                               " bytes of workspace; the static array holds " +
+                               std::to_string((size_t)CL_NOALLOC_BYTES));
+  // tables and parameters into the array (from host memory that lives until the final wait)
+  std::vector<double> params(2 * B);
+  for (int64_t i = 0; i < B; ++i) { params[i] = m_host[i]; params[B + i] = mu_host[i]; }
+  auto put = [&](void* dst, const void* src, size_t n) -> int {
+    if (n) HIPCHK(hipMemcpyAsync(dst, src, n, hipMemcpyHostToDevice, b.st));
+    return 0;
+  };
+  if ((rc = put(b.dblob, b.L.blob.data(), b.L.blob.size())) ||
+      (rc = put(b.d_front_sites, P.front_sites.data(), P.front_sites.size() * 4)) ||
+      (rc = put(b.d_site_coords, P.site_coords.data(), P.site_coords.size() * 4)) ||
+      (rc = put(b.d_inv, P.inv_maps.data(), P.inv_maps.size() * 4)) ||
+      (rc = put(b.d_rel, P.rel_maps.data(), P.rel_maps.size() * 4)) ||
+      (rc = put(b.d_sel_off, P.sel_off.data(), P.sel_off.size() * 8)) ||
+      (rc = put(b.d_sel_ld, P.sel_ld.data(), P.sel_ld.size() * 4)))
+    return rc;
+  if (b.L.R > 0 &&
+      ((rc = put(b.smw_blob_r, b.smw_r.blob.data(), b.smw_r.blob.size())) ||
+       (rc = put(b.smw_blob_l, b.smw_l.blob.data(), b.smw_l.blob.size())) ||
+       (rc = put(b.d_pivglob, b.L.pivot_global.data(), b.L.pivot_global.size() * 4))))
+    return rc;
+  // the parameters go straight to the array (a batch stages them in pinned memory)
+  b.params_host = params.data();
+  if ((rc = enqueue_factor(&b, links_dev, true)) || (rc = enqueue_selinv(&b)) ||
+      (sel_out && (rc = enqueue_selected(&b, sel_out))) || (drift_out && (rc = enqueue_drift(&b, drift_out))))
+    return rc;
+  HIPCHK(hipMemcpyAsync(status_host, b.status, sizeof(int32_t) * B, hipMemcpyDeviceToHost, b.st));
+  HIPCHK(hipStreamSynchronize(b.st));
+  b.params_host = nullptr;
+  return 0;
+}
+
 int cl_run(cl_batch b, const void* links_dev, const double* m_host, const double* mu_host,
            void* sel_out, void* drift_out) {
   if (!b || !links_dev || !m_host || !mu_host) return fail(CL_EINVAL, "null argument");
