@@ -66,6 +66,9 @@ struct GemmDesc {
   // 1: sum K in chunks of kKChunk, the running sum kept in C between chunks (C must not
   // alias A, B or C0); 0: one chain of products over all of K
   int kblock;
+  // solve launches: 1 (M) or 2 (N) is the right-hand-side extent, cut per configuration
+  // to its live count; 0: none
+  int lim_dim;
   // has_c0 = 2 (Schur complement S = A_SS - A_SJ U^): A_SS is the sum over the children
   // of their update blocks at the mapped positions, read here instead of from an
   // assembled copy. Output (row, col) is front entry (kid_base + row, kid_base + col).

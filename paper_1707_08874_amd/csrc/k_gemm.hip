@@ -53,6 +53,8 @@ struct GemmCtx {
   const int32_t* inv_maps;  // plan: front row -> child update row (Schur with has_c0 = 2)
   double2* ext;             // a caller's buffer (pool kPoolExt), per-configuration stride
   int64_t ext_stride;
+  const int32_t* lim;       // per-configuration count of live right-hand sides (lim_dim)
+  int64_t lim_stride;
 };
 
 __device__ __forceinline__ double2* pool_ptr(const GemmCtx& g, int b, int pool) {
@@ -71,9 +73,10 @@ struct Operands {
 };
 
 template <int MODE, int RA>
-__device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE, RA>& o, int r, int t) {
+__device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE, RA>& o, int r, int t,
+                                       int Mv) {
   const double2 z = make_double2(0.0, 0.0);
-  if (t >= d.K || o.ai[r] >= d.M) return z;
+  if (t >= d.K || o.ai[r] >= Mv) return z;
   if (MODE == 2) {
     const int i = o.ai[r] + d.row_base;
     if (i >= d.k && i < d.k + d.nbk) return make_double2(i - d.k == t ? -1.0 : 0.0, 0.0);
@@ -108,6 +111,17 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   const int64_t tile = (int64_t)bid - d.tile_start;
   const int row0 = (int)(tile / d.tiles_n) * BM;
   const int col0 = (int)(tile % d.tiles_n) * BN;
+  // the product's extent; in the solves the right-hand sides past this configuration's
+  // live count are neither read nor written (their columns or rows of the result stay
+  // as they were; the kernels that read them skip them too)
+  int Mv = d.M, Nv = d.N;
+  if constexpr (SOLVE) {
+    if (d.lim_dim) {
+      const int c = g.lim[b * g.lim_stride];
+      if (d.lim_dim == 1) Mv = min(Mv, c); else Nv = min(Nv, c);
+      if (row0 >= Mv || col0 >= Nv) return;  // uniform over the work-group
+    }
+  }
 
   __shared__ double2 As[NBUF][BK][BM + 1];  // +1: the k-strided stores spread over banks
   __shared__ double2 Bs[NBUF][BK][BN + 1];
@@ -134,7 +148,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     const int i = row0 + a_m0 + a_mstep * r;
     o.ai[r] = i;
     o.arow[r] = nullptr;
-    if (i < d.M) {
+    if (i < Mv) {
       if (MODE == 0) o.arow[r] = pool_ptr(g, b, d.a_pool) + d.a_off + (int64_t)i * d.lda;
       else if (MODE == 1) o.arow[r] = W + d.pinv_off + (int64_t)i * d.nbk;
       else o.arow[r] = F + d.x_off + (int64_t)IW[d.rmap_off + d.row_base + i] * d.ld + d.k;
@@ -148,7 +162,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   auto ld_b = [&](int t) __attribute__((always_inline)) -> double2 {
     const double2 z = make_double2(0.0, 0.0);
     const int j = bcol;
-    if (t >= d.K || j >= d.N) return z;
+    if (t >= d.K || j >= Nv) return z;
     if (MODE == 0) return o.bbase[(int64_t)t * d.ldb + j];
     if (MODE == 1) {
       if (j >= d.k && j < d.k + d.nbk) return make_double2(j - d.k == t ? 1.0 : 0.0, 0.0);
@@ -179,9 +193,9 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   // keeps them in scalar registers and branches on scalars).
   constexpr int kSlots = TM * TN;
   constexpr bool kRoundRobin = MODE == 0;
-  const bool interior = row0 + BM <= d.M && col0 + BN <= d.N;
+  const bool interior = row0 + BM <= Mv && col0 + BN <= Nv;
   const int wave_u = __builtin_amdgcn_readfirstlane(wave);
-  const int vr = (min(BM, d.M - row0) + 15) / 16, vc = (min(BN, d.N - col0) + 15) / 16;
+  const int vr = (min(BM, Mv - row0) + 15) / 16, vc = (min(BN, Nv - col0) + 15) / 16;
   int srow[kSlots], scol[kSlots];
   bool sok[kSlots];
 #pragma unroll
@@ -201,7 +215,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 
   auto load_stage = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk);
+    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk, Mv);
 #pragma unroll
     for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + b_kk0 + b_kstep * r);
   };
@@ -322,7 +336,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
       for (int r = 0; r < 4; ++r) {
         const int row = row0 + srow[t] + 4 * r + lr;
         const int col = col0 + scol[t] + lc;
-        if (sok[t] && row < d.M && col < d.N) {
+        if (sok[t] && row < Mv && col < Nv) {
           double2* pc = C + (int64_t)row * d.ldc + col;
           double2 v = make_double2(cr[i][j][r], ci[i][j][r]);
           if (!first) v = cadd(v, *pc);
@@ -411,7 +425,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
         // mode 1 runs the interior mapping on every tile
         const int row = row0 + (MODE == 1 ? wm * (BM / 2) + i * 16 : srow[t]) + 4 * r + l4;
         const int col = col0 + (MODE == 1 ? wn * (BN / 2) + j * 16 : scol[t]) + l16;
-        if ((MODE != 1 && !sok[t]) || row >= d.M || col >= d.N) continue;
+        if ((MODE != 1 && !sok[t]) || row >= Mv || col >= Nv) continue;
         double2 acc = make_double2(cr[i][j][r], ci[i][j][r]);
         if (MODE == 0) {
           if (chunked) acc = cadd(acc, pool_ptr(g, b, d.c_pool)[d.c_off + (int64_t)row * d.ldc + col]);
@@ -449,9 +463,9 @@ void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* 
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
                  int64_t rhs_stride, const int32_t* inv_maps, double2* ext, int64_t ext_stride,
-                 bool solve) {
+                 bool solve, const int32_t* lim, int64_t lim_stride) {
   GemmCtx g{fronts, cfg_stride, pool_elems, ws, ws_stride, iws, iws_stride, rhs, rhs_stride, inv_maps,
-            ext, ext_stride};
+            ext, ext_stride, lim, lim_stride};
   const dim3 blk(kGemmThreads);
   if (solve) hipLaunchKernelGGL((k_gemm<0, 2, 2, 8, 2, true>), grid, blk, 0, st, descs, ndesc, g);
   else if (mode == 0 && tile == kTile128) hipLaunchKernelGGL((k_gemm<0, 4, 4, 16, 1>), grid, blk, 0, st, descs, ndesc, g);

@@ -93,6 +93,11 @@ k_smw_residual(SmwCtx c, const double2* __restrict__ links, const double2* __res
   const int k = (int)(e - x * c.R);
   const double2* S = c.ws + b * c.ws_stride + (trans ? c.y_off : c.x_off);
   double2* out = c.ws + b * c.ws_stride + c.r_off;
+  if (k >= c.iws[b * c.iws_stride + c.cnt_off]) {  // a column past the perturbations: zero
+#pragma unroll
+    for (int i = 0; i < 3; ++i) out[(3 * x + i) * c.R + k] = make_double2(0.0, 0.0);
+    return;
+  }
   const double m = mvals[b], mu = muvals[b];
   const double emu = exp(mu), emu_inv = exp(-mu);
   const int R = c.R;

@@ -41,12 +41,14 @@ template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_rhs_assemble(const RhsAsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ rhs,
                int64_t rhs_stride, const double2* __restrict__ b, int64_t b_stride,
-               const int32_t* __restrict__ front_sites, const int32_t* __restrict__ inv_maps, int ns) {
+               const int32_t* __restrict__ front_sites, const int32_t* __restrict__ inv_maps, int ns,
+               const int32_t* __restrict__ lim, int64_t lim_stride) {
   const int cfg = blockIdx.y;
   const RhsAsmDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.H * ns) return;
   const int I = (int)(e / ns), col = (int)(e - (e / ns) * ns);
+  if (lim && col >= lim[cfg * lim_stride]) return;  // past the live right-hand sides
   double2* R = rhs + cfg * rhs_stride;
   double2 v = make_double2(0.0, 0.0);
   if (I < d.p) {
@@ -66,12 +68,14 @@ k_rhs_assemble(const RhsAsmDesc* __restrict__ descs, int ndesc, double2* __restr
 template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_rhs_gather(const RhsGatherDesc* __restrict__ descs, int ndesc, double2* __restrict__ rhs,
-             int64_t rhs_stride, const int32_t* __restrict__ rel_maps, int ns) {
+             int64_t rhs_stride, const int32_t* __restrict__ rel_maps, int ns,
+             const int32_t* __restrict__ lim, int64_t lim_stride) {
   const int cfg = blockIdx.y;
   const RhsGatherDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.s * ns) return;
   const int r = (int)(e / ns), col = (int)(e - (e / ns) * ns);
+  if (lim && col >= lim[cfg * lim_stride]) return;
   double2* R = rhs + cfg * rhs_stride;
   const int H = d.p + d.s;
   const double2 x = R[rhs_at<TRANS>(d.par_xoff, rel_maps[d.rel_off + r], col, d.par_H, ns)];
@@ -84,29 +88,38 @@ template <bool TRANS>
 __global__ void __launch_bounds__(256)
 k_sol_scatter(const SolScatterDesc* __restrict__ descs, int ndesc, const double2* __restrict__ rhs,
               int64_t rhs_stride, double2* __restrict__ x, int64_t x_stride,
-              const int32_t* __restrict__ front_sites, int ns, int accumulate) {
+              const int32_t* __restrict__ front_sites, int ns, int accumulate,
+              const int32_t* __restrict__ lim, int64_t lim_stride) {
   const int cfg = blockIdx.y;
   const SolScatterDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.p * ns) return;
   const int I = (int)(e / ns), col = (int)(e - (e / ns) * ns);
   const int site = front_sites[d.site_off + I / 3];
-  double2 v = rhs[cfg * rhs_stride + rhs_at<TRANS>(d.xoff, I, col, d.H, ns)];
   double2* dst = x + cfg * x_stride + ((int64_t)site * 3 + I % 3) * ns + col;
+  if (lim && col >= lim[cfg * lim_stride]) {  // the solution of a zero right-hand side
+    *dst = make_double2(0.0, 0.0);
+    return;
+  }
+  double2 v = rhs[cfg * rhs_stride + rhs_at<TRANS>(d.xoff, I, col, d.H, ns)];
   if (accumulate) v = cadd(v, *dst);
   *dst = v;
 }
 
 template __global__ void k_rhs_assemble<false>(const RhsAsmDesc*, int, double2*, int64_t, const double2*,
-                                               int64_t, const int32_t*, const int32_t*, int);
+                                               int64_t, const int32_t*, const int32_t*, int,
+                                               const int32_t*, int64_t);
 template __global__ void k_rhs_assemble<true>(const RhsAsmDesc*, int, double2*, int64_t, const double2*,
-                                              int64_t, const int32_t*, const int32_t*, int);
-template __global__ void k_rhs_gather<false>(const RhsGatherDesc*, int, double2*, int64_t, const int32_t*, int);
-template __global__ void k_rhs_gather<true>(const RhsGatherDesc*, int, double2*, int64_t, const int32_t*, int);
+                                              int64_t, const int32_t*, const int32_t*, int,
+                                              const int32_t*, int64_t);
+template __global__ void k_rhs_gather<false>(const RhsGatherDesc*, int, double2*, int64_t, const int32_t*, int,
+                                             const int32_t*, int64_t);
+template __global__ void k_rhs_gather<true>(const RhsGatherDesc*, int, double2*, int64_t, const int32_t*, int,
+                                            const int32_t*, int64_t);
 template __global__ void k_sol_scatter<false>(const SolScatterDesc*, int, const double2*, int64_t, double2*,
-                                              int64_t, const int32_t*, int, int);
+                                              int64_t, const int32_t*, int, int, const int32_t*, int64_t);
 template __global__ void k_sol_scatter<true>(const SolScatterDesc*, int, const double2*, int64_t, double2*,
-                                             int64_t, const int32_t*, int, int);
+                                             int64_t, const int32_t*, int, int, const int32_t*, int64_t);
 
 // Z~_{x,y} = (1/n) sum_s X_{x,s} xi_{y,s}^*, y in {x, x+nu, x-nu} (periodic sites),
 // written in the slot order of the selected blocks. One thread per (site, slot, entry).

@@ -54,14 +54,15 @@ __global__ void k_langevin_update(const double2* links_in, double2* links_out, c
 template <bool TRANS>
 __global__ void k_rhs_assemble(const RhsAsmDesc* descs, int ndesc, double2* rhs, int64_t rhs_stride,
                                const double2* b, int64_t b_stride, const int32_t* front_sites,
-                               const int32_t* inv_maps, int ns);
+                               const int32_t* inv_maps, int ns, const int32_t* lim, int64_t lim_stride);
 template <bool TRANS>
 __global__ void k_rhs_gather(const RhsGatherDesc* descs, int ndesc, double2* rhs, int64_t rhs_stride,
-                             const int32_t* rel_maps, int ns);
+                             const int32_t* rel_maps, int ns, const int32_t* lim, int64_t lim_stride);
 template <bool TRANS>
 __global__ void k_sol_scatter(const SolScatterDesc* descs, int ndesc, const double2* rhs,
                               int64_t rhs_stride, double2* x, int64_t x_stride,
-                              const int32_t* front_sites, int ns, int accumulate);
+                              const int32_t* front_sites, int ns, int accumulate, const int32_t* lim,
+                              int64_t lim_stride);
 __global__ void k_stochastic_blocks(const double2* x, const double2* xi, LatticeDims dims, int64_t V,
                                     int ns, double2* out);
 
@@ -82,6 +83,7 @@ void launch_gemm(int mode, int tile, dim3 grid, hipStream_t st, const GemmDesc* 
                  double2* fronts, int64_t cfg_stride, int64_t pool_elems, double2* ws,
                  int64_t ws_stride, const int32_t* iws, int64_t iws_stride, double2* rhs,
                  int64_t rhs_stride, const int32_t* inv_maps, double2* ext = nullptr,
-                 int64_t ext_stride = 0, bool solve = false);
+                 int64_t ext_stride = 0, bool solve = false, const int32_t* lim = nullptr,
+                 int64_t lim_stride = 0);
 
 }  // namespace clsel

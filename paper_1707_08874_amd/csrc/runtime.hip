@@ -559,6 +559,7 @@ enum SolveKind { kRhsAsm = 10, kRhsGather, kSolScatter };
 struct SolveLayout {
   int ns = 0;               // right-hand sides
   bool trans = false;       // left solves (row vectors): front blocks stored ns x H
+  bool live = false;        // right-hand sides past the per-configuration count are skipped
   int64_t rhs_elems = 0;    // complex workspace per configuration: R and X blocks
   int64_t stride = 0;       // per-configuration stride of the workspace (rhs_elems + extra)
   int64_t t_off = 0;        // extra region: rows j_k of the solution (R x ns), if any
@@ -575,10 +576,12 @@ struct SolveLayout {
 // backward, with the front blocks stored ns x H. With lowrank > 0 the workspace has room
 // for T = rows j_k of the solution and corr holds x -= (X C) T (right solves only).
 void build_solve_layout(const clsel::Plan& P, const Layout& L, int ns, bool trans, int lowrank,
-                        SolveLayout& S) {
+                        SolveLayout& S, bool live = false) {
   S = SolveLayout{};
   S.ns = ns;
   S.trans = trans;
+  S.live = live;
+  const int lim_dim = live ? (trans ? 1 : 2) : 0;
   const size_t nf = P.fronts.size();
   std::vector<int64_t> roff(nf), xoff(nf);
   int64_t acc = 0;
@@ -625,6 +628,7 @@ void build_solve_layout(const clsel::Plan& P, const Layout& L, int ns, bool tran
       }
       g.c0_pool = g.c_pool; g.c0_off = g.c_off; g.ldc0 = g.ldc;
       g.has_c0 = 1;
+      g.lim_dim = lim_dim;
       gs.push_back(g);
     }
     S.fwd.push_back({kRhsAsm, blob_push(S.blob, ad.data(), ad.size() * sizeof(ad[0])), (int)ad.size(), blk, tr});
@@ -658,6 +662,7 @@ void build_solve_layout(const clsel::Plan& P, const Layout& L, int ns, bool tran
         g.c_pool = clsel::kPoolRhs; g.c_off = xoff[f]; g.ldc = fr.H;
       }
       g.alpha = 1.0; g.has_c0 = 0;
+      g.lim_dim = lim_dim;
       gs.push_back(g);
     }
     if (!gd.empty())
@@ -700,6 +705,8 @@ bool validate_solve_layout(const clsel::Plan& P, const Layout& L, const SolveLay
     for (int i = 0; i < l.count; ++i) {
       const clsel::GemmDesc& g = d[i];
       if (g.mode != 0 || g.tile_start != t || g.kblock != 0) return bad("solve gemm table");
+      if (g.lim_dim != (S.live ? (S.trans ? 1 : 2) : 0) && !(&l == &S.corr && g.lim_dim == 0))
+        return bad("solve gemm right-hand-side limit");
       t += cdiv64(g.M, 64) * g.tiles_n;
       auto lim = [&](int pid) -> int64_t {
         if (pid == clsel::kPoolRhs) return S.stride;
@@ -1186,8 +1193,8 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
   TRY(upload(&b->d_sel_ld, P.sel_ld));
   if (b->L.R > 0) {  // the correction's right and left solves, R right-hand sides each
     std::string why;
-    build_solve_layout(P, b->L, b->L.R, false, 0, b->smw_r);
-    build_solve_layout(P, b->L, b->L.R, true, 0, b->smw_l);
+    build_solve_layout(P, b->L, b->L.R, false, 0, b->smw_r, true);
+    build_solve_layout(P, b->L, b->L.R, true, 0, b->smw_l, true);
     if (!validate_solve_layout(P, b->L, b->smw_r, why) || !validate_solve_layout(P, b->L, b->smw_l, why)) {
       free_batch(b);
       return fail(CL_EINVAL, "low-rank solve table check failed: " + why);
@@ -1354,6 +1361,8 @@ int run_solve(cl_batch b, const SolveLayout& S, const char* dblob, double2* ws_r
   const clsel::Plan& P = b->plan->P;
   const int B = b->active, ns = S.ns;
   const int64_t stride = S.stride;
+  const int32_t* lim = S.live ? b->iws + b->L.cnt_off : nullptr;
+  const int64_t lst = b->L.iws_elems;
   auto run = [&](const Launch& l) -> int {
     if (l.gridx <= 0) return 0;
     const dim3 grid((unsigned)l.gridx, (unsigned)B);
@@ -1362,31 +1371,35 @@ int run_solve(cl_batch b, const SolveLayout& S, const char* dblob, double2* ws_r
       case kRhsAsm:
         if (l.rpt)
           hipLaunchKernelGGL(clsel::k_rhs_assemble<true>, grid, dim3(256), 0, b->st, (const clsel::RhsAsmDesc*)dp,
-                             l.count, ws_rhs, stride, (const double2*)in, in_stride, b->d_front_sites, b->d_inv, ns);
+                             l.count, ws_rhs, stride, (const double2*)in, in_stride, b->d_front_sites, b->d_inv, ns,
+                             lim, lst);
         else
           hipLaunchKernelGGL(clsel::k_rhs_assemble<false>, grid, dim3(256), 0, b->st, (const clsel::RhsAsmDesc*)dp,
-                             l.count, ws_rhs, stride, (const double2*)in, in_stride, b->d_front_sites, b->d_inv, ns);
+                             l.count, ws_rhs, stride, (const double2*)in, in_stride, b->d_front_sites, b->d_inv, ns,
+                             lim, lst);
         break;
       case kRhsGather:
         if (l.rpt)
           hipLaunchKernelGGL(clsel::k_rhs_gather<true>, grid, dim3(256), 0, b->st, (const clsel::RhsGatherDesc*)dp,
-                             l.count, ws_rhs, stride, b->d_rel, ns);
+                             l.count, ws_rhs, stride, b->d_rel, ns, lim, lst);
         else
           hipLaunchKernelGGL(clsel::k_rhs_gather<false>, grid, dim3(256), 0, b->st, (const clsel::RhsGatherDesc*)dp,
-                             l.count, ws_rhs, stride, b->d_rel, ns);
+                             l.count, ws_rhs, stride, b->d_rel, ns, lim, lst);
         break;
       case kSolScatter:
         if (l.rpt)
           hipLaunchKernelGGL(clsel::k_sol_scatter<true>, grid, dim3(256), 0, b->st, (const clsel::SolScatterDesc*)dp,
-                             l.count, ws_rhs, stride, (double2*)out, out_stride, b->d_front_sites, ns, accumulate);
+                             l.count, ws_rhs, stride, (double2*)out, out_stride, b->d_front_sites, ns, accumulate,
+                             lim, lst);
         else
           hipLaunchKernelGGL(clsel::k_sol_scatter<false>, grid, dim3(256), 0, b->st, (const clsel::SolScatterDesc*)dp,
-                             l.count, ws_rhs, stride, (double2*)out, out_stride, b->d_front_sites, ns, accumulate);
+                             l.count, ws_rhs, stride, (double2*)out, out_stride, b->d_front_sites, ns, accumulate,
+                             lim, lst);
         break;
       default:
         clsel::launch_gemm(l.rpt, l.tile, grid, b->st, (const clsel::GemmDesc*)dp, l.count, b->fronts,
                            b->L.cfg_stride, P.pool_elems, b->ws, b->L.ws_elems, b->iws, b->L.iws_elems,
-                           ws_rhs, stride, b->d_inv, (double2*)out, out_stride, true);
+                           ws_rhs, stride, b->d_inv, (double2*)out, out_stride, true, lim, lst);
     }
     HIPCHK(hipGetLastError());
     return 0;
@@ -1588,8 +1601,8 @@ int cl_run_noalloc(cl_plan plan, int32_t batch, const void* links_dev, const dou
   std::string why;
   if (!validate_layout(P, b.L, why)) return fail(CL_EINVAL, "launch table check failed: " + why);
   if (b.L.R > 0) {
-    build_solve_layout(P, b.L, b.L.R, false, 0, b.smw_r);
-    build_solve_layout(P, b.L, b.L.R, true, 0, b.smw_l);
+    build_solve_layout(P, b.L, b.L.R, false, 0, b.smw_r, true);
+    build_solve_layout(P, b.L, b.L.R, true, 0, b.smw_l, true);
     if (!validate_solve_layout(P, b.L, b.smw_r, why) || !validate_solve_layout(P, b.L, b.smw_l, why))
       return fail(CL_EINVAL, "low-rank solve table check failed: " + why);
   }
