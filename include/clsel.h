@@ -62,7 +62,7 @@ typedef struct cl_batch_s* cl_batch;
 /* Options of the symbolic analysis. Zero fields take the defaults. */
 typedef struct {
   int32_t leaf_sites;     /* nested dissection stops at boxes of <= this many sites (default 4) */
-  int32_t max_pivot_rows; /* separators with more rows are split into a chain (<= 1536, default 1024) */
+  int32_t max_pivot_rows; /* separators with more rows are split into a chain (<= 1536, default 1536) */
   int32_t nb;             /* block width of the frontal Gauss-Jordan sweep (1..64, default 64) */
   int32_t time_cuts;      /* 1: separators may cut the time direction; 0 (default): never */
   int32_t gemm_tile;      /* output tile of the plain products: 0 auto (64 x 64), 64, 12864, 128 */

@@ -19,7 +19,10 @@ What it computes, by plain definition (Sec. 3 of the paper):
 * the complex Langevin step around it (Eqs. 3-5): the Wilson gauge action and its
   drift, and the Euler update with an optional adaptive step (oracle/langevin.py),
 * the stochastic estimate of the drift that selected inversion replaces (Eq. 7,
-  oracle/stochastic.py).
+  oracle/stochastic.py),
+* columns of D^{-1} on lattices too large for the dense inverse, by solves refined
+  against D until the residual stops falling (oracle/frontal.py), for reference blocks
+  and drifts around sampled sites.
 
 Pins: see tests/test_oracle_pins.py. Every function here is pinned by at least
 one test that does not reuse the function's own formula.
@@ -33,6 +36,7 @@ from .columns import inverse_columns, sampled_selected_check
 from .langevin import (plaquettes, wilson_action, staples, gauge_drift, drift_norm_max,
                        step_size, langevin_step)
 from .stochastic import solve_dense, stochastic_blocks, stochastic_drift
+from .frontal import FrontalLU, column_blocks
 
 __all__ = [
     "coords", "eta_phases", "hop_tables", "dirac_dense", "dirac_sparse",
@@ -40,5 +44,5 @@ __all__ = [
     "drift_from_blocks", "selected_and_drift", "SLOT_NAMES", "chiral_condensate",
     "number_density", "inverse_columns", "sampled_selected_check", "plaquettes",
     "wilson_action", "staples", "gauge_drift", "drift_norm_max", "step_size", "langevin_step",
-    "solve_dense", "stochastic_blocks", "stochastic_drift",
+    "solve_dense", "stochastic_blocks", "stochastic_drift", "FrontalLU", "column_blocks",
 ]

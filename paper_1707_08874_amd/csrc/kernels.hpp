@@ -16,7 +16,7 @@ constexpr int kMaxPivotRows = 1536;   // pivot rows per supernode the panel kern
 // K-chunk of the blocked summation of the plain GEMMs: each output sums kKChunk products
 // in the matrix-core accumulator, then adds that partial sum to its running total
 constexpr int kKChunk = 128;
-constexpr int kMaxChunks = 12;        // longer K: chunks of ceil(K / kMaxChunks) products (whole stages)
+constexpr int kMaxChunks = 96;        // longer K: chunks of ceil(K / kMaxChunks) products (whole stages)
 // front assembly and Z_SS gather: tile of one 256-thread work-group (one column per thread)
 constexpr int kAsmTileRows = 8, kAsmTileCols = 256;
 constexpr int kMaxLowRank = 1024;     // columns of the low-rank correction

@@ -20,7 +20,7 @@ constexpr int kMaxChildren = 4;
 
 struct PlanOptions {
   int leaf_sites = 4;       // boxes with at most this many sites become leaves
-  int max_pivot_rows = 1024;  // cap on p (rows) per supernode; larger separators are chunked
+  int max_pivot_rows = 1536;  // cap on p (rows) per supernode; larger separators are chunked
   int nb = 64;              // block width of the frontal Gauss-Jordan sweep
   int time_cuts = 0;        // 0: separators never cut the time direction, 1: allowed
   int gemm_tile = 0;        // plain-product tile: 0 auto (64), 64, 12864 (128 x 64) or 128
