@@ -237,6 +237,12 @@ int cl_batch_profile_read(cl_batch batch, double* gemm_ms, double* gemm_flops, d
  * stream. NULL arrays are allowed only with cap == 0. */
 int cl_batch_profile_launches(cl_batch batch, int64_t cap, double* ms, double* flops,
                               double* bytes, int32_t* mode, int64_t* n);
+/* Test support (failure injection): in every following factorisation the assembled pivot
+ * block of front `front` (an index of cl_plan_export table 0) of configuration `config` is
+ * zero, as if D were singular there. front < 0 turns it off. The configuration then reports
+ * CL_ESINGULAR (no perturbation: zero pivots) or CL_ERANK (more perturbed pivots than the
+ * cap) with NaN outputs, and the other configurations are unaffected. */
+int cl_batch_inject_fault(cl_batch batch, int32_t config, int32_t front);
 /* Number of perturbed pivots of each active configuration in the last factorisation
  * (host array of batch entries; waits for the stream). */
 int cl_batch_perturbations(cl_batch batch, int32_t* per_config_host);

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libclsel.so")
-SOURCES = ["plan.cpp", "runtime.hip", "k_assemble.hip", "k_panel.hip", "k_gemm.hip", "k_gather.hip",
+SOURCES = ["plan.cpp", "layout.cpp", "runtime.hip", "k_assemble.hip", "k_panel.hip", "k_gemm.hip", "k_gather.hip",
            "k_langevin.hip", "k_solve.hip", "k_smw.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

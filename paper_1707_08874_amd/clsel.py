@@ -53,7 +53,7 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
            "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables",
            "cl_gauge_drift", "cl_langevin_update", "cl_solve", "cl_stochastic_blocks",
-           "cl_drift_from_blocks", "cl_batch_perturbations", "cl_run_noalloc"]
+           "cl_drift_from_blocks", "cl_batch_perturbations", "cl_run_noalloc", "cl_batch_inject_fault"]
 
 
 def lib():
@@ -99,6 +99,7 @@ def lib():
         "cl_drift_from_blocks": (ctypes.c_int, [vp, vp, vp]),
         "cl_batch_perturbations": (ctypes.c_int, [vp, i32p]),
         "cl_run_noalloc": (ctypes.c_int, [vp, ctypes.c_int32, vp, dp, dp, vp, vp, i32p, vp]),
+        "cl_batch_inject_fault": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -354,6 +355,11 @@ class Batch:
         out = np.zeros(self.active, dtype=np.int32)
         _check(lib().cl_status(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
         return out
+
+    def inject_fault(self, config: int, front: int):
+        """Test support: zero the assembled pivot block of one front of one configuration in
+        the following factorisations (front < 0: off)."""
+        _check(lib().cl_batch_inject_fault(self._h, int(config), int(front)))
 
     def perturbations(self) -> np.ndarray:
         """Perturbed pivots of each active configuration in the last factorisation."""

@@ -32,6 +32,7 @@ struct AsmDesc {
   int child_p[4];
   int child_ld[4];
   int64_t rowid_off;      // iws: p entries initialised to the identity
+  int front_id;           // the front's index in the plan
 };
 
 // Panel of the frontal Gauss-Jordan sweep: one entry per (front, block step).

@@ -90,7 +90,7 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
            const double2* __restrict__ links,
            const double2* __restrict__ linv, int64_t link_cfg_stride,
            const double* __restrict__ mvals, const double* __restrict__ muvals, LatticeDims dims,
-           int32_t* __restrict__ iws, int64_t iws_stride) {
+           int32_t* __restrict__ iws, int64_t iws_stride, int fault_cfg, int fault_front) {
   constexpr int kRows = kAsmTileRows;
   const int b = blockIdx.y;
   int lo = 0, hi = ndesc - 1;
@@ -147,6 +147,9 @@ k_assemble(const AsmDesc* __restrict__ descs, int ndesc, double2* __restrict__ f
     if (!ipiv && !jpiv) continue;
     const int x = front_sites[d.site_off + I / 3];
     v[k] = cadd(v[k], dirac_entry(x, I % 3, y, bj, site_coords[x], py, U, Ui, m, mu, dims));
+    // test support (cl_batch_inject_fault): the pivot block of one front of one
+    // configuration is assembled as zero
+    if (b == fault_cfg && d.front_id == fault_front && ipiv && jpiv) v[k] = make_double2(0.0, 0.0);
     F[(ipiv ? d.joff : d.off) + (int64_t)I * d.ld + J] = v[k];
   }
   if (I0 == 0 && jpiv) iws[b * iws_stride + d.rowid_off + J] = J;

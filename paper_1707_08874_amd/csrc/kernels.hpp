@@ -4,24 +4,11 @@
 
 #include <cstdint>
 
+#include "consts.hpp"
 #include "desc.hpp"
 #include "device.hpp"
 
 namespace clsel {
-
-constexpr int kMaxNB = 64;            // widest Gauss-Jordan block
-// output tiles of the plain (mode 0) GEMMs
-constexpr int kTile64 = 64, kTile128x64 = 12864, kTile128 = 128;
-constexpr int kMaxPivotRows = 1536;   // pivot rows per supernode the panel kernel can hold
-// K-chunk of the blocked summation of the plain GEMMs: each output sums kKChunk products
-// in the matrix-core accumulator, then adds that partial sum to its running total
-constexpr int kKChunk = 128;
-constexpr int kMaxChunks = 96;        // longer K: chunks of ceil(K / kMaxChunks) products (whole stages)
-// front assembly and Z_SS gather: tile of one 256-thread work-group (one column per thread)
-constexpr int kAsmTileRows = 8, kAsmTileCols = 256;
-constexpr int kMaxLowRank = 1024;     // columns of the low-rank correction
-constexpr int32_t kStatusSingular = -4;
-constexpr int32_t kStatusNonFinite = -5;
 
 __global__ void k_link_inverse(const double2* links, double2* linv, int64_t links_per_cfg,
                                int nbatch, int32_t* status);
@@ -29,7 +16,8 @@ __global__ void k_assemble(const AsmDesc* descs, int ndesc, double2* fronts, int
                            const int32_t* front_sites, const int32_t* inv_maps,
                            const uint32_t* site_coords, const double2* links, const double2* linv,
                            int64_t link_cfg_stride, const double* mvals, const double* muvals,
-                           LatticeDims dims, int32_t* iws, int64_t iws_stride);
+                           LatticeDims dims, int32_t* iws, int64_t iws_stride, int fault_cfg,
+                           int fault_front);
 __global__ void k_gather_zss(const GatherDesc* descs, int ndesc, double2* fronts,
                              int64_t cfg_stride, const int32_t* rel_maps);
 __global__ void k_gather_selected(const double2* fronts, int64_t cfg_stride,

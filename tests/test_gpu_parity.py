@@ -186,3 +186,37 @@ def test_observables_match_oracle(torch_cuda):
         n = oracle.number_density(ref_sel, U[b], dims, m[b], mu[b])
         assert abs(obs[b, 0] - sig) <= tol * abs(sig), (b, obs[b, 0], sig)
         assert abs(obs[b, 1] - n) <= tol * max(abs(n), abs(sig)), (b, obs[b, 1], n)
+
+
+@pytest.mark.parametrize("floor,code", [(-1.0, clsel.CL_ESINGULAR), (0.0, clsel.CL_ERANK)],
+                         ids=["no-perturbation", "perturbation"])
+def test_injected_singular_pivot_block_is_isolated(torch_cuda, floor, code):
+    """Failure injection: the assembled pivot block of the largest front of one
+    configuration is zero. Without pivot perturbation its pivots are zero (CL_ESINGULAR);
+    with it, all of them are perturbed, more than the correction can undo (CL_ERANK). The
+    configuration's outputs are NaN, the others are bitwise those of a clean run, and
+    turning the fault off restores every configuration."""
+    torch = torch_cuda
+    dims = (4, 4, 4, 4)
+    U = gen_batch(dims, [0, 1, 2])
+    plan = clsel.Plan(dims, pivot_floor=floor)
+    fr = plan.fronts()
+    big = max(range(len(fr)), key=lambda f: fr[f]["p"])
+    assert fr[big]["p"] > plan.info()["lowrank_cap"] or floor < 0
+    lt = torch.from_numpy(U).to("cuda")
+    batch = clsel.Batch(plan, 3)
+    s0, d0 = (t.cpu().numpy() for t in batch.run(lt, M, MU))
+    assert batch.status().tolist() == [0, 0, 0]
+    print(f"\n[gpu] fault in front {big} (p = {fr[big]['p']}) of configuration 1, floor {floor}", flush=True)
+    batch.inject_fault(1, big)
+    s1, d1 = (t.cpu().numpy() for t in batch.run(lt, M, MU))
+    st = batch.status().tolist()
+    assert st == [0, code, 0], st
+    assert np.all(np.isnan(s1[1])) and np.all(np.isnan(d1[1]))
+    for c in (0, 2):
+        assert np.array_equal(s1[c], s0[c]) and np.array_equal(d1[c], d0[c]), c
+    batch.inject_fault(0, -1)
+    s2, d2 = (t.cpu().numpy() for t in batch.run(lt, M, MU))
+    assert batch.status().tolist() == [0, 0, 0]
+    assert np.array_equal(s2, s0) and np.array_equal(d2, d0)
+    batch.close()
