@@ -99,6 +99,12 @@ def main():
     ap.add_argument("--parity-sweep", type=int, default=0, metavar="K",
                     help="run the batched step once and check its first K configurations against "
                          "the CPU oracle, one line per configuration")
+    ap.add_argument("--serve", action="store_true",
+                    help="the serving stream (Poisson arrivals of 4^4 / 6^4 / 8^3x4 / 12^3x6 requests): "
+                         "saturated capacity, then p50/p99 latency and throughput at --serve-load of it")
+    ap.add_argument("--serve-load", type=float, default=0.8)
+    ap.add_argument("--serve-seconds", type=float, default=20.0)
+    ap.add_argument("--serve-burst", type=int, default=300)
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--max-pivot-rows", type=int, default=0)
@@ -124,6 +130,8 @@ def main():
         return library_gemm(args)
     if args.parity_sweep:
         return parity_sweep(args)
+    if args.serve:
+        return serve(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -622,6 +630,69 @@ def langevin(args):
            "eps_used_range": [float(np.min(eps_used)), float(np.max(eps_used))],
            "status_ok": bool((st == 0).all())}
     print(json.dumps(out))
+
+
+def serve(args):
+    """Continuous batching of a mixed-lattice request stream (4^4, 6^4, 8^3x4, 12^3x6 with
+    weights 0.3 each and 0.1; m in {0.02, 0.05, 0.1}, mu ~ U[0, 0.4], eps ~ U[0, 0.3]).
+    A burst of --serve-burst requests at once measures the saturated capacity; then
+    Poisson arrivals at --serve-load of that capacity for --serve-seconds give the
+    latency distribution (arrival to results on the host) and the throughput. A sample
+    of the served results is checked against the oracle at 1e-10."""
+    import oracle
+    from paper_1707_08874_amd.serve import Server, make_requests, summarize
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import TOL, block_errors, drift_errors
+
+    def run(reqs, label):
+        srv = Server()
+        srv.warm(sorted({r.dims for r in reqs}))
+        t = time.perf_counter()
+        done = srv.run(reqs)
+        wall = time.perf_counter() - t
+        out = summarize(done, wall)
+        out.update(budget_bytes=srv.budget, peak_bytes=srv.peak_used)
+        srv.close()
+        print(f"[bench] serve {label}: {len(done)} requests in {wall:.1f}s, "
+              f"{out['throughput_req_s']:.1f} req/s, p50 {out['p50_ms']:.0f} ms, "
+              f"p99 {out['p99_ms']:.0f} ms", file=sys.stderr, flush=True)
+        return done, out
+
+    _, sat = run(make_requests(args.serve_burst, rate=1e7, seed=1), "saturated")
+    cap = sat["throughput_req_s"]
+    rate = args.serve_load * cap
+    n = max(20, int(round(rate * args.serve_seconds)))
+    done, res = run(make_requests(n, rate=rate, seed=0), f"load {args.serve_load}")
+
+    # oracle parity on the first served requests of the two smallest shapes
+    worst, checked = 0.0, 0
+    for dims in ((4, 4, 4, 4), (6, 6, 6, 6)):
+        for r in [r for r in done if r.dims == dims][:2]:
+            Z = oracle.inverse_dense(oracle.dirac_dense(r.links, r.dims, r.m, r.mu))
+            ref = oracle.selected_blocks(Z, r.dims)
+            dref = oracle.drift_from_blocks(ref, r.links, r.dims, r.mu)
+            worst = max(worst, float(block_errors(r.selected, ref).max()),
+                        float(drift_errors(r.drift, dref).max()))
+            checked += 1
+    line = {
+        "metric": "served selected inversions+drift/sec, mixed lattices; p50/p99 latency",
+        "value": res["throughput_req_s"], "unit": "requests/s", "higher_is_better": True,
+        "n_gpus": 1, "dtype": "c128", "data": "synthetic",
+        "offered_load": args.serve_load, "offered_req_s": rate, "capacity_req_s": cap,
+        "p50_ms": res["p50_ms"], "p90_ms": res["p90_ms"], "p99_ms": res["p99_ms"],
+        "requests": res["requests"], "failed": res["failed"], "mean_batch": res["mean_batch"],
+        "device_overlap": res["device_overlap"], "by_shape": res["by_shape"],
+        "saturated": {k: sat[k] for k in ("throughput_req_s", "p50_ms", "p99_ms", "mean_batch")},
+        "peak_hbm_bytes": res["peak_bytes"], "hbm_budget_bytes": res["budget_bytes"],
+        "parity": {"checked": checked, "worst_rel": worst, "tol": TOL, "ok": worst <= TOL},
+        "config": {"workload": "serving stream: Poisson arrivals, 4^4 / 6^4 / 8^3x4 / 12^3x6 lattices "
+                               "with weights 0.3 / 0.3 / 0.3 / 0.1",
+                   "m": [0.02, 0.05, 0.1], "mu": [0.0, 0.4], "eps": [0.0, 0.3],
+                   "seconds": args.serve_seconds},
+    }
+    print(json.dumps(line))
+    if res["failed"] or not line["parity"]["ok"]:
+        sys.exit(1)
 
 
 def scaling(args):

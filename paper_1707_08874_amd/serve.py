@@ -45,6 +45,9 @@ class Request:
     drift: np.ndarray | None = None
     status: int = 0
     batch_size: int = 0
+    slot_id: int = -1
+    dev_start_ms: float = -1.0    # device time of the launch's start and end (HIP events on
+    dev_end_ms: float = -1.0      # its slot stream), in ms after the run's reference event
 
     @property
     def latency(self) -> float:
@@ -67,7 +70,9 @@ class _Slot:
     busy: bool = False
     reqs: list = field(default_factory=list)
     event: object = None
+    start_event: object = None
     last_used: float = 0.0
+    sid: int = 0
 
 
 class Server:
@@ -94,6 +99,8 @@ class Server:
         self.peak_used = 0
         self.done: list[Request] = []
         self.t0 = time.perf_counter()
+        self.nslots = 0
+        self.ref_event = None  # device-time origin of the current run
 
     # ---------------------------------------------------------------- plans and slots
     def plan(self, dims) -> clsel.Plan:
@@ -140,7 +147,8 @@ class Server:
                      host_sel=torch.empty((cap, V, 9, 3, 3), dtype=torch.complex128, pin_memory=True)
                      if self.keep_selected else None,
                      host_drift=torch.empty((cap, V, 4, 8), dtype=torch.complex128, pin_memory=True),
-                     nbytes=need)
+                     nbytes=need, sid=self.nslots)
+        self.nslots += 1
         self.slots[dims].append(slot)
         self.used += need
         self.peak_used = max(self.peak_used, self.used)
@@ -187,6 +195,8 @@ class Server:
         mu = np.array([r.mu for r in reqs])
         slot.batch.set_active(n)
         with torch.cuda.stream(slot.stream):
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev0.record(slot.stream)
             slot.links[:n].copy_(slot.host_links[:n], non_blocking=True)
             slot.batch.run(slot.links[:n], m, mu,
                            slot.sel[:n] if slot.sel is not None else None, slot.drift[:n],
@@ -194,16 +204,21 @@ class Server:
             if slot.sel is not None:
                 slot.host_sel[:n].copy_(slot.sel[:n], non_blocking=True)
             slot.host_drift[:n].copy_(slot.drift[:n], non_blocking=True)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(slot.stream)
         slot.event = ev
+        slot.start_event = ev0
         slot.reqs = reqs
         slot.busy = True
 
     def _finish(self, slot: _Slot):
         now = self.now()
         st = slot.batch.status()
+        t_start = self.ref_event.elapsed_time(slot.start_event) if self.ref_event is not None else -1.0
+        t_end = self.ref_event.elapsed_time(slot.event) if self.ref_event is not None else -1.0
         for i, r in enumerate(slot.reqs):
+            r.slot_id = slot.sid
+            r.dev_start_ms, r.dev_end_ms = t_start, t_end
             if slot.host_sel is not None:
                 r.selected = slot.host_sel[i].numpy().copy()
             r.drift = slot.host_drift[i].numpy().copy()
@@ -243,6 +258,8 @@ class Server:
     def run(self, requests: list[Request]) -> list[Request]:
         """Replays the requests at their arrival times (seconds from now) until all are done."""
         pending = sorted(requests, key=lambda r: r.arrival)
+        self.ref_event = self.torch.cuda.Event(enable_timing=True)
+        self.ref_event.record()
         self.t0 = time.perf_counter()
         i = 0
         while i < len(pending) or self.busy():
@@ -288,6 +305,31 @@ def make_requests(n: int, rate: float, seed: int = 0, mix=DEFAULT_MIX, pool: int
     return reqs
 
 
+def device_overlap(reqs: list[Request]) -> dict:
+    """Pairs of launches from different slots whose device intervals (start and end events
+    on their slot streams) intersect, and the device time during which two or more slots
+    had work in flight, as a fraction of the span of all launches."""
+    launches = sorted({(r.slot_id, r.dev_start_ms, r.dev_end_ms) for r in reqs if r.dev_end_ms >= 0},
+                      key=lambda t: t[1])
+    pairs = 0
+    for i, (si, a0, a1) in enumerate(launches):
+        for sj, b0, b1 in launches[i + 1:]:
+            if b0 >= a1:
+                break
+            if sj != si and min(a1, b1) > max(a0, b0):
+                pairs += 1
+    edges = sorted([(a, 1) for _, a, _ in launches] + [(b, -1) for _, _, b in launches])
+    depth, last, multi = 0, None, 0.0
+    for t, dlt in edges:
+        if last is not None and depth >= 2:
+            multi += t - last
+        depth += dlt
+        last = t
+    span = (launches[-1][2] - launches[0][1]) if launches else 0.0
+    return {"launches": len(launches), "overlapping_pairs": pairs,
+            "multi_slot_fraction": multi / span if span > 0 else 0.0}
+
+
 def summarize(reqs: list[Request], wall: float) -> dict:
     lat = np.array([r.latency for r in reqs])
     by = collections.defaultdict(list)
@@ -307,6 +349,7 @@ def summarize(reqs: list[Request], wall: float) -> dict:
         "p90_ms": float(np.percentile(lat, 90) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_batch": float(np.mean([r.batch_size for r in reqs])),
+        "device_overlap": device_overlap(reqs),
         "by_shape": per_shape,
         "failed": int(sum(r.status != 0 for r in reqs)),
     }

@@ -3,13 +3,15 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1707_08874_amd import clsel
-from paper_1707_08874_amd.serve import Server, make_requests
+from paper_1707_08874_amd import autotune, clsel
+from paper_1707_08874_amd.serve import Server, device_overlap, make_requests
 from parity import TOL, assert_parity
 
 pytestmark = pytest.mark.gpu
 
 MIX = (((4, 4, 4, 4), 0.4), ((4, 4, 4, 6), 0.3), ((6, 4, 4, 4), 0.3))
+# the serving workload's shapes that fit a test's time: 4^4, 6^4 and 8^3x4
+REAL_MIX = (((4, 4, 4, 4), 0.4), ((6, 6, 6, 6), 0.3), ((8, 8, 8, 4), 0.3))
 
 
 @pytest.fixture(scope="module")
@@ -21,7 +23,7 @@ def torch_cuda():
 
 
 def _alone(torch, r):
-    plan = clsel.Plan(r.dims)
+    plan = clsel.Plan(r.dims, **autotune.options(r.dims, 1))  # the server's plan options
     b = clsel.Batch(plan, 1)
     lt = torch.from_numpy(r.links[None].copy()).to("cuda")
     sel, drift = b.run(lt, [r.m], [r.mu])
@@ -60,3 +62,36 @@ def test_budget_forces_queueing_and_eviction(torch_cuda):
     srv.close()
     assert len(done) == 12 and all(r.status == 0 for r in done)
     assert srv.peak_used <= srv.budget
+
+
+def test_real_mix_overlaps_on_device_and_equals_alone(torch_cuda):
+    """4^4, 6^4 and 8^3x4 requests arriving together: slots of different shapes (and two
+    slots of one shape) have device intervals, from HIP events recorded on their own
+    streams, that intersect; every result equals the same request run alone, bit for
+    bit, and matches the oracle on the two smaller shapes."""
+    reqs = make_requests(24, rate=1e6, seed=5, mix=REAL_MIX, pool=3)
+    shapes = sorted({r.dims for r in reqs})
+    assert len(shapes) == 3, shapes
+    srv = Server(hbm_budget=int(24e9), slot_bytes_target=1e12, max_capacity=4)
+    srv.warm(shapes)
+    done = srv.run(reqs)
+    srv.close()
+    assert len(done) == 24 and all(r.status == 0 for r in done)
+    assert srv.peak_used <= srv.budget
+    ov = device_overlap(done)
+    print("device overlap:", ov)
+    assert ov["launches"] >= 3
+    assert ov["overlapping_pairs"] >= 1, "no two slots had work on the device at the same time"
+    pairs = {(a.slot_id, b.slot_id) for a in done for b in done
+             if a.slot_id != b.slot_id and min(a.dev_end_ms, b.dev_end_ms) > max(a.dev_start_ms, b.dev_start_ms)}
+    assert pairs
+    for dims in shapes:
+        r = next(r for r in done if r.dims == dims)
+        s1, d1 = _alone(torch_cuda, r)
+        assert np.array_equal(r.selected, s1) and np.array_equal(r.drift, d1), (dims, r.rid)
+    for dims in ((4, 4, 4, 4), (6, 6, 6, 6)):
+        r = next(r for r in done if r.dims == dims)
+        Z = oracle.inverse_dense(oracle.dirac_dense(r.links, r.dims, r.m, r.mu))
+        ref = oracle.selected_blocks(Z, r.dims)
+        assert_parity(r.selected, r.drift, ref, oracle.drift_from_blocks(ref, r.links, r.dims, r.mu),
+                      TOL, label=str(dims))
