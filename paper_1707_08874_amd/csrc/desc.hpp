@@ -38,7 +38,7 @@ struct AsmDesc {
 // Panel of the frontal Gauss-Jordan sweep: one entry per (front, block step).
 struct PanelDesc {
   int64_t x_off;          // front offset in the input pool (incl. pool)
-  int64_t pw_off;         // ws: (p-k) x nb panel copy
+  int64_t pw_off;         // ws: (p-k) x nb panel copy, column-major
   int64_t pinv_off;       // ws: nb x nb inverse of the pivot block
   int64_t piv_off;        // iws: nb pivot rows (rows of the input front)
   int64_t rmap_off;       // iws: H entries, new row -> old row

@@ -4,7 +4,7 @@
 // candidates (row pivoting stays inside the supernode's own rows), this kernel
 //   phase 1: picks the nbk pivot rows by partial pivoting (largest modulus, lowest
 //            row on ties), running an in-place Gauss-Jordan elimination of the
-//            candidate rows over the panel columns in register groups of 16
+//            candidate rows over the panel columns in register groups of 8 to 16
 //            columns, with the remaining groups updated lazily in a workspace copy;
 //            per column: a DPP arg-max in each wave, the wave winners' rows through
 //            LDS, one barrier, a DPP combine of the eight wave results;
@@ -28,8 +28,15 @@ namespace clsel {
 
 constexpr int kPanelThreads = 512;
 constexpr int kWaves = kPanelThreads / 64;
-constexpr int kGroup = 16;
 constexpr int kPiLd = kMaxNB + 1;
+// Registers per thread: RPT rows x G columns of the current group (4 VGPRs per complex
+// value) plus RPT x CH accumulators of the lazy update must stay within the 256 VGPRs a
+// wave has at two waves per SIMD; narrower groups for more rows per thread keep the
+// kernel free of scratch spills.
+template <int RPT> struct PanelShape;
+template <> struct PanelShape<1> { static constexpr int G = 16, CH = 8; };
+template <> struct PanelShape<2> { static constexpr int G = 12, CH = 8; };
+template <> struct PanelShape<3> { static constexpr int G = 8, CH = 4; };
 
 // Cross-lane helpers for the pivot search. DPP moves stay in the vector ALU, so a
 // wave-wide reduction costs a few instructions per step and no LDS round trip.
@@ -48,42 +55,42 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
   return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
-// Largest v over the wave and, among the lanes holding it, the lowest i; every lane
-// returns both. Two passes of one instruction per step (maximum, then minimum over
-// DPP: quad permutes, row rotations by 4 and 8, row broadcasts 15 and 31), so the
-// comparison never goes through scalar condition masks. v is never NaN here.
-__device__ __forceinline__ void wave_argmax(double& v, int& i) {
-  double m = v;
+// Pivot search key of row r with |a|^2 = a2: the bits of a2 (a non-negative double)
+// with the low 11 significand bits replaced by 2047 - r. The largest key is the row of
+// largest |a|^2, compared to 41 significand bits, and among rows equal to that precision
+// the lowest one. Keys are non-negative finite doubles, which order like their bit
+// patterns, so one fmax reduction finds value and row together. A NaN ranks with zero
+// (the row stays a valid choice and the non-finite pivot is flagged); +inf becomes the
+// largest finite key. Rows out of the search take -1.
+static_assert(kMaxPivotRows <= 2048, "pivot keys hold the row in 11 bits");
+__device__ __forceinline__ double pivot_key(double a2, int r) {
+  unsigned long long u = __builtin_bit_cast(unsigned long long, a2);
+  u = (a2 == a2) ? u : 0ull;
+  u = u >= 0x7FF0000000000000ull ? 0x7FEFFFFFFFFFFFFFull : u;
+  return __builtin_bit_cast(double, (u & ~0x7FFull) | (unsigned long long)(0x7FF - r));
+}
+__device__ __forceinline__ int key_row(double key) {
+  return 0x7FF - (int)(__builtin_bit_cast(unsigned long long, key) & 0x7FFull);
+}
+// Largest key over the wave, returned to every lane: DPP quad permutes, row rotations
+// by 4 and 8, row broadcasts 15 and 31, then lane 63.
+__device__ __forceinline__ double wave_max(double m) {
   m = fmax(m, dpp_f64<0xB1, 0xF>(m));
   m = fmax(m, dpp_f64<0x4E, 0xF>(m));
   m = fmax(m, dpp_f64<0x124, 0xF>(m));
   m = fmax(m, dpp_f64<0x128, 0xF>(m));
   m = fmax(m, dpp_f64<0x142, 0xA>(m));
   m = fmax(m, dpp_f64<0x143, 0xC>(m));
-  m = readlane_f64(m, 63);
-  int k = v == m ? i : 0x7fffffff;
-  k = min(k, dpp_i32<0xB1, 0xF>(k));
-  k = min(k, dpp_i32<0x4E, 0xF>(k));
-  k = min(k, dpp_i32<0x124, 0xF>(k));
-  k = min(k, dpp_i32<0x128, 0xF>(k));
-  k = min(k, dpp_i32<0x142, 0xA>(k));
-  k = min(k, dpp_i32<0x143, 0xC>(k));
-  v = m;
-  i = __builtin_amdgcn_readlane(k, 63);
+  return readlane_f64(m, 63);
 }
-// The same over the kWaves wave results, lane l holding result l % 8.
-__device__ __forceinline__ void combine_waves(double& v, int& i) {
+// The same over the kWaves wave results, lane l holding result l % 8: each group of
+// eight lanes ends with the maximum of all eight.
+__device__ __forceinline__ double combine_waves(double m) {
   static_assert(kWaves == 8, "three DPP steps combine eight lanes");
-  double m = v;
   m = fmax(m, dpp_f64<0xB1, 0xF>(m));
   m = fmax(m, dpp_f64<0x4E, 0xF>(m));
   m = fmax(m, dpp_f64<0x124, 0xF>(m));
-  int k = v == m ? i : 0x7fffffff;
-  k = min(k, dpp_i32<0xB1, 0xF>(k));
-  k = min(k, dpp_i32<0x4E, 0xF>(k));
-  k = min(k, dpp_i32<0x124, 0xF>(k));
-  v = m;
-  i = k;
+  return m;
 }
 
 template <int RPT>
@@ -99,10 +106,10 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   double2* Pinv = ws + b * ws_stride + d.pinv_off;
   int32_t* IW = iws + b * iws_stride;
   const int cand = d.p - d.k, nbk = d.nbk, ld = d.ld, k = d.k;
+  constexpr int kGroup = PanelShape<RPT>::G;
 
   __shared__ double2 s_cand[2][kWaves][kGroup];  // each wave's best row, per column parity
-  __shared__ double s_rv[2][kWaves];
-  __shared__ int s_ri[2][kWaves];
+  __shared__ double s_key[2][kWaves];
   __shared__ int s_piv[kMaxNB];
   __shared__ double2 s_delta[kMaxNB];  // perturbation of each pivot of the block
   __shared__ int s_flag;
@@ -112,8 +119,9 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
   __shared__ int s_pos[kMaxPivotRows];
 
   // Column group 0 is read straight from the front; the lazy update after each group
-  // writes the later groups of the unused rows to PW (row-major, ld nbk), which is
-  // where groups >= 1 are read from.
+  // writes the later groups of the unused rows to PW, column-major with leading
+  // dimension cand (a wave's lanes hold consecutive rows, so its accesses to one column
+  // are contiguous), which is where groups >= 1 are read from.
   const double2* Xp = X + (int64_t)k * ld + k;  // candidate row 0, panel column 0
   if (tid == 0) s_flag = 0;
   __syncthreads();
@@ -123,6 +131,9 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
 #pragma unroll
   for (int j = 0; j < RPT; ++j) used[j] = false;
   const int lane = tid & 63, wave = tid >> 6;
+  // a wave whose first row is past the candidates holds no candidate row at all (its
+  // rows are tid + j * kPanelThreads); it only takes part in the barriers
+  const bool wave_dead = (tid & ~63) >= cand;
 
   // ---- phase 1: pivot choice
   for (int g0 = 0; g0 < nbk; g0 += kGroup) {
@@ -131,53 +142,53 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
     for (int j = 0; j < RPT; ++j) {
       const int r = tid + j * kPanelThreads;
       const bool live = r < cand && !used[j];
-      const double2* src = g0 == 0 ? Xp + (int64_t)r * ld : PW + (int64_t)r * nbk + g0;
+      // element (r, c) of the group: the front (row-major) for group 0, else PW
+      const double2* src = g0 == 0 ? Xp + (int64_t)r * ld : PW + (int64_t)g0 * cand + r;
+      const int64_t cs = g0 == 0 ? 1 : cand;
 #pragma unroll
       for (int c = 0; c < kGroup; ++c)
-        cur[j][c] = (live && c < gw) ? src[c] : make_double2(0.0, 0.0);
+        cur[j][c] = (live && c < gw) ? src[c * cs] : make_double2(0.0, 0.0);
     }
     // Each column step rotates the row registers by one slot: the column being
     // eliminated is always slot 0, the updated later columns move down one slot and
     // the multiplier goes to the last slot, so every register index is a constant.
-    // All 16 steps run (steps past the group width only rotate), which brings the frame
+    // All kGroup steps run (steps past the group width only rotate), which brings the frame
     // back: slot t then holds the multiplier of the group's pivot t.
     auto column_step = [&](int c) {
       if (c < gw) {
-        double best = -1.0;
-        int bi = 0x7fffffff;
-#pragma unroll
-        for (int j = 0; j < RPT; ++j) {
-          const int r = tid + j * kPanelThreads;
-          double a = cabs2(cur[j][0]);
-          if (!(a == a)) a = -0.5;  // NaN ranks below every number but is still a valid row
-          const bool take = r < cand && !used[j] && a > best;
-          best = take ? a : best;
-          bi = take ? r : bi;
-        }
-        wave_argmax(best, bi);
-        // the lane holding its wave's best row publishes it: one barrier per column
         const int par = c & 1;
+        if (!wave_dead) {
+          double key = -1.0;
 #pragma unroll
-        for (int j = 0; j < RPT; ++j)
-          if (tid + j * kPanelThreads == bi) {
-#pragma unroll
-            for (int cc = 0; cc < kGroup; ++cc) s_cand[par][wave][cc] = cur[j][cc];
+          for (int j = 0; j < RPT; ++j) {
+            const int r = tid + j * kPanelThreads;
+            const double kj = (r < cand && !used[j]) ? pivot_key(cabs2(cur[j][0]), r) : -1.0;
+            key = fmax(key, kj);
           }
-        if (lane == 0) { s_rv[par][wave] = best; s_ri[par][wave] = bi; }
-        __syncthreads();
-        double bb = s_rv[par][lane & (kWaves - 1)];
-        int pr = s_ri[par][lane & (kWaves - 1)];
-        combine_waves(bb, pr);
-        int ww = (pr & (kPanelThreads - 1)) >> 6;  // the wave that owns row pr
-        if (pr < 0 || pr >= cand) { pr = 0; bb = -1.0; ww = 0; }  // keeps every index in range
-        const double2* pv = s_cand[par][ww];
-        if (tid == 0) {
-          s_piv[g0 + c] = pr;
-          if (!isfinite(bb) || (!(bb > 0.0) && !(floor > 0.0))) s_flag = 1;
+          key = wave_max(key);
+          // the lane holding its wave's best row publishes it: one barrier per column
+          const int bi = key >= 0.0 ? key_row(key) : -1;
+#pragma unroll
+          for (int j = 0; j < RPT; ++j)
+            if (tid + j * kPanelThreads == bi) {
+#pragma unroll
+              for (int cc = 0; cc < kGroup; ++cc) s_cand[par][wave][cc] = cur[j][cc];
+            }
+          if (lane == 0) s_key[par][wave] = key;
+        } else if (lane == 0) {
+          s_key[par][wave] = -1.0;
         }
+        __syncthreads();
+        const double kk = combine_waves(s_key[par][lane & (kWaves - 1)]);
+        int pr = kk >= 0.0 ? key_row(kk) : -1;
+        const bool found = pr >= 0 && pr < cand;
+        if (!found) pr = 0;  // keeps every index in range; flagged below
+        const int ww = (pr & (kPanelThreads - 1)) >> 6;  // the wave that owns row pr
+        const double2* pv = s_cand[par][ww];
+        if (tid == 0) s_piv[g0 + c] = pr;
 #pragma unroll
         for (int j = 0; j < RPT; ++j) used[j] = used[j] || (tid + j * kPanelThreads == pr);
-        double2 dp = pv[0];
+        double2 dp = found ? pv[0] : make_double2(0.0, 0.0);
         const bool finite = isfinite(dp.x) && isfinite(dp.y);
         double2 delta = make_double2(0.0, 0.0);
         if (floor > 0.0 && finite && cabs2(dp) < floor * floor) {
@@ -189,12 +200,13 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
         }
         if (tid == 0) {
           s_delta[g0 + c] = delta;
-          if (!finite) s_flag = 1;
+          if (!found || !finite || !(cabs2(dp) > 0.0)) s_flag = 1;
         }
         if (!(cabs2(dp) > 0.0) || !finite) dp = make_double2(1.0, 0.0);
         const double2 invd = crecip(dp);
-        // rows out of the elimination (pivots, rows past the candidates) take a zero
-        // multiplier and only rotate; their values are not read again
+        // rows out of the elimination (pivots, rows past the candidates, every row of a
+        // wave past the candidates) take a zero multiplier and only rotate; their values
+        // are not read again
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const bool live = tid + j * kPanelThreads < cand && !used[j];
@@ -214,39 +226,36 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
         }
       }
     };
-    // unrolled by 4 where the registers allow it (renaming makes the rotation free)
-    if constexpr (RPT <= 2) {
+    // unrolled by 4 (register renaming makes the rotation free)
 #pragma unroll 4
-      for (int c = 0; c < kGroup; ++c) column_step(c);
-    } else {
-#pragma unroll 1
-      for (int c = 0; c < kGroup; ++c) column_step(c);
-    }
+    for (int c = 0; c < kGroup; ++c) column_step(c);
     __syncthreads();  // s_piv of this group
     // lazy update of the later column groups of the still-unused rows:
-    // PW[r][cc] += sum_t W_r[t] * R[t][cc], R = group pivot rows at group start
+    // PW(r, cc) += sum_t W_r[t] * R[t][cc], R = group pivot rows at group start
     const int rest0 = g0 + gw, nrest = nbk - rest0;
     if (nrest > 0) {
       for (int e = tid; e < gw * nrest; e += kPanelThreads) {
         const int t = e / nrest, cc = e % nrest;
         const int pr = s_piv[g0 + t];
         s_buf[t * kMaxNB + cc] = g0 == 0 ? Xp[(int64_t)pr * ld + rest0 + cc]
-                                         : PW[(int64_t)pr * nbk + rest0 + cc];
+                                         : PW[(int64_t)(rest0 + cc) * cand + pr];
       }
       __syncthreads();
       // the loads of a chunk of columns of all RPT rows are issued together, so that
       // 8 * RPT loads per thread are in flight before the first product needs one
-      constexpr int kChunk = 8;
-      for (int c0 = 0; c0 < nrest; c0 += kChunk) {
+      constexpr int kChunk = PanelShape<RPT>::CH;
+      for (int c0 = 0; c0 < nrest && !wave_dead; c0 += kChunk) {
         double2 acc[RPT][kChunk];
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const int r = tid + j * kPanelThreads;
           const bool ok = r < cand && !used[j];
-          const double2* src = g0 == 0 ? Xp + (int64_t)r * ld + rest0 : PW + (int64_t)r * nbk + rest0;
+          const double2* src = g0 == 0 ? Xp + (int64_t)r * ld + rest0 + c0
+                                       : PW + (int64_t)(rest0 + c0) * cand + r;
+          const int64_t cs = g0 == 0 ? 1 : cand;
 #pragma unroll
           for (int q = 0; q < kChunk; ++q)
-            acc[j][q] = (ok && c0 + q < nrest) ? src[c0 + q] : make_double2(0.0, 0.0);
+            acc[j][q] = (ok && c0 + q < nrest) ? src[q * cs] : make_double2(0.0, 0.0);
         }
         // each pivot-row value is read from LDS once per chunk and used for all RPT rows
         // (the sum over t runs in the same order for every element)
@@ -265,10 +274,10 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
         for (int j = 0; j < RPT; ++j) {
           const int r = tid + j * kPanelThreads;
           if (r < cand && !used[j]) {
-            double2* dst = PW + (int64_t)r * nbk + rest0;
+            double2* dst = PW + (int64_t)(rest0 + c0) * cand + r;
 #pragma unroll
             for (int q = 0; q < kChunk; ++q)
-              if (c0 + q < nrest) dst[c0 + q] = acc[j][q];
+              if (c0 + q < nrest) dst[(int64_t)q * cand] = acc[j][q];
           }
         }
       }
