@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-burst", type=int, default=300)
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes of the batched step (0: automatic, 1, or 2 streams)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--max-pivot-rows", type=int, default=0)
@@ -167,6 +169,7 @@ def main():
     # ---- batched path: the whole step replayed from one HIP graph, nothing else in the timed loop
     batch = clsel.Batch(plan, B)
     batch.use_graph(True)
+    batch.set_lanes(args.lanes)
     for _ in range(max(args.warmup, 1)):  # the first call captures the graph
         batch.run(lt, m, mu, sel, drift)
     batch.sync()

@@ -112,6 +112,15 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
 int cl_batch_set_active(cl_batch batch, int32_t n);
 /* Enables (1) or disables (0) HIP-graph capture of cl_run. */
 int cl_batch_use_graph(cl_batch batch, int32_t enable);
+/* Lanes of cl_run: 1 runs the active configurations as one batch on the batch stream;
+ * 2 runs the first half there and the second half on a second stream of the batch,
+ * forked from it and joined back before cl_run's work ends (also under graph capture),
+ * so that the latency-bound kernels of one half (pivot panels, assembly, gathers) run
+ * beside the matrix-core products of the other. Every configuration is computed by the
+ * same kernels either way, so the results are bitwise the same. 0 (the default) picks
+ * 2 from 16 active configurations on, else 1; while GEMM launches are timed
+ * (cl_batch_profile) cl_run uses one lane. CL_EINVAL outside 0..2. */
+int cl_batch_set_lanes(cl_batch batch, int32_t lanes);
 /* Assembles D for each configuration from `links_dev` (device, [B][V][4][3][3]
  * complex128, copied before the call returns control of it to the stream) and
  * m_host[b], mu_host[b], then runs the supernodal factorisation (partial

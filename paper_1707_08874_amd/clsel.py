@@ -53,7 +53,8 @@ EXPORTS = ["cl_symbolic", "cl_symbolic_ex", "cl_plan_info", "cl_plan_bytes", "cl
            "cl_batch_sync", "cl_batch_destroy", "cl_strerror", "cl_last_error",
            "cl_batch_profile", "cl_batch_profile_read", "cl_batch_profile_launches", "cl_batch_query", "cl_observables",
            "cl_gauge_drift", "cl_langevin_update", "cl_solve", "cl_stochastic_blocks",
-           "cl_drift_from_blocks", "cl_batch_perturbations", "cl_run_noalloc", "cl_batch_inject_fault"]
+           "cl_drift_from_blocks", "cl_batch_perturbations", "cl_run_noalloc", "cl_batch_inject_fault",
+           "cl_batch_set_lanes"]
 
 
 def lib():
@@ -100,6 +101,7 @@ def lib():
         "cl_batch_perturbations": (ctypes.c_int, [vp, i32p]),
         "cl_run_noalloc": (ctypes.c_int, [vp, ctypes.c_int32, vp, dp, dp, vp, vp, i32p, vp]),
         "cl_batch_inject_fault": (ctypes.c_int, [vp, ctypes.c_int32, ctypes.c_int32]),
+        "cl_batch_set_lanes": (ctypes.c_int, [vp, ctypes.c_int32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -219,6 +221,11 @@ class Batch:
     def set_active(self, n: int):
         _check(lib().cl_batch_set_active(self._h, int(n)))
         self.active = int(n)
+
+    def set_lanes(self, lanes: int):
+        """0: automatic; 1: one stream; 2: the second half of the configurations on a second
+        stream of the batch (see cl_batch_set_lanes)."""
+        _check(lib().cl_batch_set_lanes(self._h, int(lanes)))
 
     def use_graph(self, enable: bool = True):
         _check(lib().cl_batch_use_graph(self._h, 1 if enable else 0))

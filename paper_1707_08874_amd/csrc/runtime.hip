@@ -73,6 +73,12 @@ struct cl_batch_s {
   int device = 0;
   hipStream_t user = nullptr, st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_param = nullptr;
+  // cl_run in two lanes: the second half of the configurations on a second stream
+  // (forked from and joined back to st), so that the latency-bound kernels of one half
+  // (pivot panels, assembly, gathers) run beside the other half's GEMMs
+  hipStream_t st2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int lanes = 0;  // 0: two lanes from kAutoLaneBatch active configurations, else 1 or 2
   double2* fronts = nullptr;
   double2* ws = nullptr;
   int32_t* iws = nullptr;
@@ -108,6 +114,7 @@ struct cl_batch_s {
   int fault_cfg = -1, fault_front = -1;  // test support: a zeroed pivot block
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
+  int g_lanes = 0;
   const void* g_links = nullptr;
   void* g_sel = nullptr;
   void* g_drift = nullptr;
@@ -211,13 +218,18 @@ int enqueue_launches(cl_batch b, const std::vector<Launch>& ls) {
 int enqueue_smw(cl_batch b);
 clsel::SmwCtx smw_ctx(cl_batch b);
 
-int enqueue_factor(cl_batch b, const void* links_dev, bool capturing) {
-  const clsel::Plan& P = b->plan->P;
-  const int B = b->active;
+int upload_params(cl_batch b, bool capturing) {
   HIPCHK(hipMemcpyAsync(b->params, b->params_host, sizeof(double) * 2 * b->cap,
                         hipMemcpyHostToDevice, b->st));
   // marks the pinned staging buffer reusable; under capture it is recorded after the launch
   if (!capturing) HIPCHK(hipEventRecord(b->ev_param, b->st));
+  return 0;
+}
+
+// The factorisation of the active configurations; m and mu are already on the device.
+int enqueue_factor_body(cl_batch b, const void* links_dev) {
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active;
   HIPCHK(hipMemcpyAsync(b->links, links_dev, sizeof(double2) * b->L.links_elems * B,
                         hipMemcpyDeviceToDevice, b->st));
   hipLaunchKernelGGL(k_fill_i32, dim3((B + 255) / 256), dim3(256), 0, b->st, b->status, B, 0);
@@ -232,6 +244,11 @@ int enqueue_factor(cl_batch b, const void* links_dev, bool capturing) {
   hipLaunchKernelGGL(clsel::k_smw_list, dim3(B), dim3(256), 0, b->st, smw_ctx(b));
   HIPCHK(hipGetLastError());
   return 0;
+}
+
+int enqueue_factor(cl_batch b, const void* links_dev, bool capturing) {
+  int rc = upload_params(b, capturing);
+  return rc ? rc : enqueue_factor_body(b, links_dev);
 }
 
 int enqueue_selinv(cl_batch b) {
@@ -261,6 +278,97 @@ int enqueue_drift(cl_batch b, void* out) {
                      b->links, b->linv, b->params + b->cap, ldims(P), P.V, B, (double2*)out);
   HIPCHK(hipGetLastError());
   return 0;
+}
+
+// Configurations [b0, b0 + n) of the batch as a batch of n on stream st, for the scope of
+// this object: every per-configuration buffer pointer moves to configuration b0 (the
+// kernels address configuration blockIdx.y from those pointers and their per-configuration
+// strides) and is put back at the end. Host-side only; a batch is not used concurrently.
+class SubBatch {
+ public:
+  SubBatch(cl_batch b, int b0, int n, hipStream_t st) : b_(b), s_(*b) {
+    const Layout& L = b->L;
+    b->fronts += b0 * L.cfg_stride;
+    b->ws += b0 * L.ws_elems;
+    b->iws += b0 * L.iws_elems;
+    b->links += b0 * L.links_elems;
+    b->linv += b0 * L.links_elems;
+    b->sel += b0 * L.sel_elems;
+    b->params += b0;  // m at [0, cap), mu at [cap, 2 cap): both move by b0
+    b->lparams += b0;
+    b->kmax += b0;
+    b->status += b0;
+    if (b->rhs) b->rhs += b0 * b->solve.stride;
+    if (b->smw_rhs) b->smw_rhs += b0 * std::max(b->smw_r.stride, b->smw_l.stride);
+    b->fault_cfg = (b->fault_cfg >= b0 && b->fault_cfg < b0 + n) ? b->fault_cfg - b0 : -1;
+    b->active = n;
+    b->st = st;
+  }
+  ~SubBatch() { s_.put(b_); }
+  SubBatch(const SubBatch&) = delete;
+  SubBatch& operator=(const SubBatch&) = delete;
+
+ private:
+  struct Saved {
+    double2 *fronts, *ws, *links, *linv, *sel, *rhs, *smw_rhs;
+    int32_t *iws, *status;
+    double *params, *lparams;
+    unsigned long long* kmax;
+    int active, fault_cfg;
+    hipStream_t st;
+    explicit Saved(const cl_batch_s& b)
+        : fronts(b.fronts), ws(b.ws), links(b.links), linv(b.linv), sel(b.sel), rhs(b.rhs),
+          smw_rhs(b.smw_rhs), iws(b.iws), status(b.status), params(b.params), lparams(b.lparams),
+          kmax(b.kmax), active(b.active), fault_cfg(b.fault_cfg), st(b.st) {}
+    void put(cl_batch b) const {
+      b->fronts = fronts; b->ws = ws; b->links = links; b->linv = linv; b->sel = sel; b->rhs = rhs;
+      b->smw_rhs = smw_rhs; b->iws = iws; b->status = status; b->params = params;
+      b->lparams = lparams; b->kmax = kmax; b->active = active; b->fault_cfg = fault_cfg; b->st = st;
+    }
+  };
+  cl_batch b_;
+  Saved s_;
+};
+
+// Lanes cl_run uses for the active configurations: two from this many on (each half keeps
+// enough configurations to fill the device in its GEMM launches), unless set explicitly;
+// one while GEMM launches are being timed.
+constexpr int kAutoLaneBatch = 16;
+int run_lanes(cl_batch b) {
+  if (b->prof || b->active < 2) return 1;
+  if (b->lanes) return b->lanes;
+  return b->active >= kAutoLaneBatch ? 2 : 1;
+}
+
+// cl_run's work: factorisation, selected inversion with the low-rank correction,
+// selected blocks and drift of the active configurations, in one or two lanes.
+int enqueue_run(cl_batch b, const void* links_dev, void* sel_out, void* drift_out, bool capturing) {
+  int rc = upload_params(b, capturing);
+  if (rc) return rc;
+  auto body = [&](const void* lk, void* so, void* dr) -> int {
+    int r = enqueue_factor_body(b, lk);
+    if (!r) r = enqueue_selinv(b);
+    if (!r && so) r = enqueue_selected(b, so);
+    if (!r && dr) r = enqueue_drift(b, dr);
+    return r;
+  };
+  const int nl = run_lanes(b);
+  if (nl == 1) return body(links_dev, sel_out, drift_out);
+  const clsel::Plan& P = b->plan->P;
+  const int B = b->active, h = B / 2;
+  HIPCHK(hipEventRecord(b->ev_fork, b->st));
+  HIPCHK(hipStreamWaitEvent(b->st2, b->ev_fork, 0));
+  for (int lane = 0; lane < 2 && !rc; ++lane) {
+    const int b0 = lane ? h : 0, n = lane ? B - h : h;
+    SubBatch sb(b, b0, n, lane ? b->st2 : b->st);
+    rc = body((const double2*)links_dev + b0 * b->L.links_elems,
+              sel_out ? (void*)((double2*)sel_out + b0 * b->L.sel_elems) : nullptr,
+              drift_out ? (void*)((double2*)drift_out + b0 * P.V * 32) : nullptr);
+  }
+  // the join is recorded even after an error, so that a capture still ends on st
+  HIPCHK(hipEventRecord(b->ev_join, b->st2));
+  HIPCHK(hipStreamWaitEvent(b->st, b->ev_join, 0));
+  return rc;
 }
 
 int begin(cl_batch b) {
@@ -303,6 +411,9 @@ void free_batch(cl_batch b) {
   if (b->ev_in) hipEventDestroy(b->ev_in);
   if (b->ev_out) hipEventDestroy(b->ev_out);
   if (b->ev_param) hipEventDestroy(b->ev_param);
+  if (b->ev_fork) hipEventDestroy(b->ev_fork);
+  if (b->ev_join) hipEventDestroy(b->ev_join);
+  if (b->st2) hipStreamDestroy(b->st2);
   if (b->st) hipStreamDestroy(b->st);
   delete b;
 }
@@ -447,6 +558,9 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
   HTRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
   HTRY(hipEventCreateWithFlags(&b->ev_param, hipEventDisableTiming));
   HTRY(hipEventRecord(b->ev_param, b->st));
+  HTRY(hipStreamCreateWithFlags(&b->st2, hipStreamNonBlocking));
+  HTRY(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming));
+  HTRY(hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming));
   const int64_t B = batch;
   TRY(dalloc(&b->fronts, (size_t)(B * b->L.cfg_stride)));
   TRY(dalloc(&b->ws, (size_t)(B * b->L.ws_elems)));
@@ -490,7 +604,8 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
     HTRY(hipMemcpy(b->smw_blob_r, b->smw_r.blob.data(), b->smw_r.blob.size(), hipMemcpyHostToDevice));
     TRY(dalloc(&b->smw_blob_l, b->smw_l.blob.size()));
     HTRY(hipMemcpy(b->smw_blob_l, b->smw_l.blob.data(), b->smw_l.blob.size(), hipMemcpyHostToDevice));
-    TRY(dalloc(&b->smw_rhs, (size_t)(b->smw_r.stride * B)));
+    // the right and left solves take turns in one workspace
+    TRY(dalloc(&b->smw_rhs, (size_t)(std::max(b->smw_r.stride, b->smw_l.stride) * B)));
     TRY(upload(&b->d_pivglob, b->L.pivot_global));
   }
   HTRY(hipMemset(b->status, 0, sizeof(int32_t) * B));
@@ -503,6 +618,12 @@ int cl_batch_create(cl_plan plan, int32_t batch, void* hip_stream, cl_batch* out
 int cl_batch_set_active(cl_batch b, int32_t n) {
   if (!b || n < 1 || n > b->cap) return fail(CL_EINVAL, "active count out of range");
   if (n != b->active) { b->active = n; b->state = 0; }
+  return 0;
+}
+
+int cl_batch_set_lanes(cl_batch b, int32_t lanes) {
+  if (!b || lanes < 0 || lanes > 2) return fail(CL_EINVAL, "lanes must be 0 (automatic), 1 or 2");
+  b->lanes = lanes;
   return 0;
 }
 
@@ -961,19 +1082,13 @@ int cl_run(cl_batch b, const void* links_dev, const double* m_host, const double
   if ((rc = begin(b))) return rc;
   if ((rc = stage_params(b, m_host, mu_host))) return rc;
   if (!b->use_graph) {
-    if ((rc = enqueue_factor(b, links_dev, false))) return rc;
-    if ((rc = enqueue_selinv(b))) return rc;
-    if (sel_out && (rc = enqueue_selected(b, sel_out))) return rc;
-    if (drift_out && (rc = enqueue_drift(b, drift_out))) return rc;
+    if ((rc = enqueue_run(b, links_dev, sel_out, drift_out, false))) return rc;
   } else {
     if (!b->gexec || b->g_links != links_dev || b->g_sel != sel_out || b->g_drift != drift_out ||
-        b->g_active != b->active) {
+        b->g_active != b->active || b->g_lanes != run_lanes(b)) {
       if (b->gexec) { hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
       HIPCHK(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
-      rc = enqueue_factor(b, links_dev, true);
-      if (!rc) rc = enqueue_selinv(b);
-      if (!rc && sel_out) rc = enqueue_selected(b, sel_out);
-      if (!rc && drift_out) rc = enqueue_drift(b, drift_out);
+      rc = enqueue_run(b, links_dev, sel_out, drift_out, true);
       hipGraph_t graph = nullptr;
       hipError_t e = hipStreamEndCapture(b->st, &graph);
       if (rc) { if (graph) hipGraphDestroy(graph); return rc; }
@@ -982,6 +1097,7 @@ int cl_run(cl_batch b, const void* links_dev, const double* m_host, const double
       hipGraphDestroy(graph);
       if (e != hipSuccess) { b->gexec = nullptr; return fail(CL_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); }
       b->g_links = links_dev; b->g_sel = sel_out; b->g_drift = drift_out; b->g_active = b->active;
+      b->g_lanes = run_lanes(b);
     }
     HIPCHK(hipGraphLaunch(b->gexec, b->st));
     HIPCHK(hipEventRecord(b->ev_param, b->st));

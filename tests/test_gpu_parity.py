@@ -220,3 +220,60 @@ def test_injected_singular_pivot_block_is_isolated(torch_cuda, floor, code):
     assert batch.status().tolist() == [0, 0, 0]
     assert np.array_equal(s2, s0) and np.array_equal(d2, d0)
     batch.close()
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_two_lanes_are_bitwise_one_lane(torch_cuda, graph):
+    """cl_run with the second half of the configurations on the batch's second stream
+    gives bitwise the results of one lane (eager and graph replay, an odd batch so the
+    halves differ), with per-configuration m and mu, statuses and perturbation counts in
+    the right places, and a fault injected in the second half stays in its configuration."""
+    torch = torch_cuda
+    dims, B = (4, 4, 4, 6), 5
+    U = gen_batch(dims, range(B))
+    ms = np.array([0.05, 0.02, 0.1, 0.05, 0.03])
+    mus = np.array([0.25, 0.0, 0.4, 0.1, 0.3])
+    plan = clsel.Plan(dims)
+    lt = torch.from_numpy(U).to("cuda")
+    out = {}
+    for lanes in (1, 2):
+        batch = clsel.Batch(plan, B)
+        batch.use_graph(graph)
+        batch.set_lanes(lanes)
+        for rep in range(2):  # a replay of the captured graph as well as its first run
+            s, d = batch.run(lt, ms, mus)
+            batch.sync()
+        out[lanes] = (s.cpu().numpy(), d.cpu().numpy(), batch.status().tolist(),
+                      batch.perturbations().tolist())
+        if lanes == 2:
+            fr = plan.fronts()
+            big = max(range(len(fr)), key=lambda f: fr[f]["p"])
+            batch.inject_fault(3, big)
+            s3, d3 = (t.cpu().numpy() for t in batch.run(lt, ms, mus))
+            st = batch.status().tolist()
+            assert st[3] != 0 and [st[c] for c in (0, 1, 2, 4)] == [0, 0, 0, 0], st
+            for c in (0, 1, 2, 4):
+                assert np.array_equal(s3[c], out[1][0][c]) and np.array_equal(d3[c], out[1][1][c]), c
+        batch.close()
+    s1, d1, st1, p1 = out[1]
+    s2, d2, st2, p2 = out[2]
+    assert st1 == st2 == [0] * B and p1 == p2
+    assert np.array_equal(s1, s2) and np.array_equal(d1, d2)
+    for c in (1, 4):  # each half against the oracle
+        ref = _oracle(U[c], dims, ms[c], mus[c])
+        assert_parity(s2[c], d2[c], ref[0], ref[1], TOL, label=str(c))
+
+
+def test_lanes_argument_checked():
+    plan = clsel.Plan((4, 4, 4, 4))
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            pytest.skip("no GPU")
+    except ImportError:
+        pytest.skip("no torch")
+    batch = clsel.Batch(plan, 2)
+    with pytest.raises(clsel.ClselError):
+        batch.set_lanes(3)
+    batch.set_lanes(0)
+    batch.close()
