@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--serve-burst", type=int, default=300)
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes of the batched step (0: automatic, 1, or 2 streams)")
+    ap.add_argument("--pivot-floor", type=float, default=0.0,
+                    help="pivot perturbation floor (0: the tuned or library default)")
+    ap.add_argument("--lowrank-cap", type=int, default=0,
+                    help="cap on perturbed pivots per configuration (0: the tuned or library default)")
     ap.add_argument("--nb", type=int, default=0)
     ap.add_argument("--leaf", type=int, default=0)
     ap.add_argument("--max-pivot-rows", type=int, default=0)
@@ -155,6 +159,10 @@ def main():
             o["leaf_sites"] = args.leaf
         if args.max_pivot_rows:
             o["max_pivot_rows"] = args.max_pivot_rows
+        if args.pivot_floor:
+            o["pivot_floor"] = args.pivot_floor
+        if args.lowrank_cap:
+            o["lowrank_cap"] = args.lowrank_cap
         return o
 
     opts_b = plan_opts(B)
@@ -463,6 +471,10 @@ def parity_sweep(args):
         opts["leaf_sites"] = args.leaf
     if args.max_pivot_rows:
         opts["max_pivot_rows"] = args.max_pivot_rows
+    if args.pivot_floor:
+        opts["pivot_floor"] = args.pivot_floor
+    if args.lowrank_cap:
+        opts["lowrank_cap"] = args.lowrank_cap
     plan = clsel.Plan(dims, **opts)
     V = plan.info()["volume"]
     links = gen_batch(dims, range(B))
@@ -477,6 +489,9 @@ def parity_sweep(args):
     batch.close()
     # the plain single-configuration plan (graph replay), on the same configurations
     opts1 = autotune.options(dims, 1)
+    for key in ("pivot_floor", "lowrank_cap"):
+        if key in opts:
+            opts1[key] = opts[key]
     pb = clsel.Batch(clsel.Plan(dims, **opts1), 1)
     pb.use_graph(True)
     sel1, drift1, status1 = [], [], []

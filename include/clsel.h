@@ -70,6 +70,8 @@ typedef struct {
                              64 per 24576 rows of D, at least 64; at most 1024) */
   double pivot_floor;     /* pivot perturbation threshold in units of D's entries (0: default 0.3;
                              negative: no perturbation). See cl_factor. */
+  int32_t smw_refine;     /* 1: one refinement step of the correction's solves against D~
+                             formed from the links; 0 (default): none (0..1) */
 } cl_plan_opts;
 
 typedef struct {
@@ -85,6 +87,7 @@ typedef struct {
   double flops_dense_inverse; /* 8 N^3: what a full inverse would cost */
   int32_t lowrank_cap;     /* columns of the low-rank correction (0: perturbation off) */
   double pivot_floor;      /* pivot perturbation threshold (negative: off) */
+  int32_t smw_refine;      /* refinement steps of the correction's solves */
 } cl_plan_info_t;
 
 /* Symbolic analysis of one lattice shape (host only, no device work). Every
@@ -138,9 +141,10 @@ int cl_factor(cl_batch batch, const void* links_dev, const double* m_host, const
  * D; then the low-rank correction of the perturbed pivots (see cl_factor):
  *   D^{-1} = D~^{-1} - X C Y,  X = D~^{-1} U,  Y = V^T D~^{-1},  C = (I + V^T X)^{-1},
  * with U = [-delta_k e_{i_k}] and V = [e_{j_k}]. X and Y come from r right and r left solves
- * through the same frontal factors, each refined once against D~ itself (the residual is
- * formed from the links); the r x r matrix C by Gauss-Jordan elimination with partial
- * pivoting. A singular C sets CL_ESINGULAR. Enqueues only. */
+ * through the same frontal factors (with the plan option smw_refine, each refined once
+ * against D~ itself, the residual formed from the links); the r x r matrix C by
+ * Gauss-Jordan elimination with partial pivoting. A singular C sets CL_ESINGULAR.
+ * Enqueues only. */
 int cl_selinv(cl_batch batch);
 /* Drift K [B][V][4][8] complex128 into out_dev (device). Enqueues only. */
 int cl_drift(cl_batch batch, void* out_dev);

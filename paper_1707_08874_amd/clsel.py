@@ -31,7 +31,8 @@ class ClselError(RuntimeError):
 class PlanOpts(ctypes.Structure):
     _fields_ = [("leaf_sites", ctypes.c_int32), ("max_pivot_rows", ctypes.c_int32),
                 ("nb", ctypes.c_int32), ("time_cuts", ctypes.c_int32), ("gemm_tile", ctypes.c_int32),
-                ("lowrank_cap", ctypes.c_int32), ("pivot_floor", ctypes.c_double)]
+                ("lowrank_cap", ctypes.c_int32), ("pivot_floor", ctypes.c_double),
+                ("smw_refine", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -42,7 +43,7 @@ class PlanInfo(ctypes.Structure):
                 ("flops_factor", ctypes.c_double), ("flops_selinv", ctypes.c_double),
                 ("flops_factor_alg", ctypes.c_double), ("flops_selinv_alg", ctypes.c_double),
                 ("flops_dense_inverse", ctypes.c_double), ("lowrank_cap", ctypes.c_int32),
-                ("pivot_floor", ctypes.c_double)]
+                ("pivot_floor", ctypes.c_double), ("smw_refine", ctypes.c_int32)]
 
 
 _lib = None
@@ -126,14 +127,15 @@ class Plan:
 
     def __init__(self, dims, leaf_sites: int = 0, max_pivot_rows: int = 0, nb: int = 0,
                  time_cuts: bool = False, gemm_tile: int = 0, lowrank_cap: int = 0,
-                 pivot_floor: float = 0.0):
+                 pivot_floor: float = 0.0, smw_refine: int = 0):
         """pivot_floor: 0 takes the library default (0.3), a negative value turns pivot
-        perturbation (and its low-rank correction) off; lowrank_cap: 0 takes the default."""
+        perturbation (and its low-rank correction) off; lowrank_cap: 0 takes the default;
+        smw_refine: 1 refines the correction's solves once against D~ (default 0)."""
         L = lib()
         self.dims = tuple(int(v) for v in dims)
         self._h = ctypes.c_void_p()
         opts = PlanOpts(leaf_sites, max_pivot_rows, nb, 1 if time_cuts else 0, gemm_tile,
-                        lowrank_cap, float(pivot_floor))
+                        lowrank_cap, float(pivot_floor), int(smw_refine))
         _check(L.cl_symbolic_ex(_dims(dims), ctypes.byref(opts), ctypes.byref(self._h)))
 
     def info(self) -> dict:

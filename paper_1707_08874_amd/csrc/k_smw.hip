@@ -7,9 +7,9 @@
 // exactly). With U = [-delta_k e_{i_k}] and V = [e_{j_k}], D = D~ + U V^T, and the
 // Sherman-Morrison-Woodbury identity gives D^{-1} exactly from D~'s factors:
 //   D^{-1} = D~^{-1} - X C Y,  X = D~^{-1} U,  Y = V^T D~^{-1},  C = (I + V^T X)^{-1}.
-// X and Y come from right and left solves through the frontal factors, each refined once
-// against D~ itself (the residual is formed from the links and the perturbation list, not
-// from the factors). The kernels below compact the perturbation list, build the
+// X and Y come from right and left solves through the frontal factors, optionally refined
+// once against D~ itself (the residual is formed from the links and the perturbation list,
+// not from the factors). The kernels below compact the perturbation list, build the
 // right-hand sides and residuals, invert the small matrix and apply -X C Y to the
 // selected blocks.
 #include "desc.hpp"
@@ -171,85 +171,106 @@ __global__ void __launch_bounds__(256) k_smw_residual_delta(SmwCtx c, int trans)
   }
 }
 
-// C = (I + V^T X)^{-1} by Gauss-Jordan elimination with partial pivoting (largest
-// modulus, lowest row on ties) on [I + V^T X | I], one work-group of 256 threads per
-// configuration. Only the leading count x count block differs from the identity. The
-// augmented left half lives in the r buffer (free at this point), the right half is C.
-__global__ void __launch_bounds__(256) k_smw_capacitance(SmwCtx c) {
+// C = (I + V^T X)^{-1}: only its leading r x r block (r = the configuration's count of
+// perturbed pivots) differs from the identity. That block is inverted in place in the r
+// buffer (free at this point) by Gauss-Jordan elimination with partial pivoting (largest
+// modulus, lowest row on ties): per column the pivot row is swapped into place and
+// scaled, every other row eliminated, and the column of the inverse kept where the
+// eliminated column was; the row interchanges are undone on the columns at the end, in
+// reverse order. One work-group of kCapThreads per configuration; the pivot row and column
+// of each step go through LDS, the elements stay in global memory (coalesced along rows).
+constexpr int kCapThreads = 1024;
+constexpr int kCapWaves = kCapThreads / 64;
+
+__device__ __forceinline__ void better(double& v, int& i, double v2, int i2) {
+  if (v2 > v || (v2 == v && i2 < i)) { v = v2; i = i2; }
+}
+
+__global__ void __launch_bounds__(kCapThreads) k_smw_capacitance(SmwCtx c) {
   const int b = blockIdx.x;
   const int32_t* IW = c.iws + b * c.iws_stride;
   double2* W = c.ws + b * c.ws_stride;
-  double2* A = W + c.r_off;
+  double2* A = W + c.r_off;  // r x r block, leading dimension R
   double2* Cm = W + c.c_off;
   const int R = c.R, r = IW[c.cnt_off];
-  const int tid = threadIdx.x;
-  for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
-    const int i = (int)(e / R), j = (int)(e % R);
-    double2 a = make_double2(i == j ? 1.0 : 0.0, 0.0);
-    if (i < r && j < r) a = cadd(a, W[c.x_off + (int64_t)IW[c.lj_off + i] * R + j]);
-    A[e] = a;
-    Cm[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
-  }
-  __shared__ double s_v[256];
-  __shared__ int s_i[256];
-  __shared__ double2 s_f[kMaxLowRank];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  __shared__ double2 s_row[kMaxLowRank];
+  __shared__ double2 s_col[kMaxLowRank];
+  __shared__ int s_perm[kMaxLowRank];
+  __shared__ double s_wv[kCapWaves];
+  __shared__ int s_wi[kCapWaves];
   __shared__ int s_bad;
+  for (int64_t e = tid; e < (int64_t)r * r; e += kCapThreads) {
+    const int i = (int)(e / r), j = (int)(e - (e / r) * r);
+    double2 a = W[c.x_off + (int64_t)IW[c.lj_off + i] * R + j];
+    if (i == j) a = cadd(a, make_double2(1.0, 0.0));
+    A[(int64_t)i * R + j] = a;
+  }
   if (tid == 0) s_bad = 0;
   __syncthreads();
-  for (int k = 0; k < r; ++k) {
-    // pivot: largest |A[i][k]| over i >= k
+  int k = 0;
+  for (; k < r; ++k) {
+    // pivot: largest |A[i][k]| over i >= k (a NaN ranks below every number)
     double best = -1.0;
     int bi = 0x7fffffff;
-    for (int i = k + tid; i < r; i += 256) {
+    for (int i = k + tid; i < r; i += kCapThreads) {
       double a = cabs2(A[(int64_t)i * R + k]);
       if (!(a == a)) a = -0.5;
-      if (a > best) { best = a; bi = i; }
+      better(best, bi, a, i);
     }
-    s_v[tid] = best;
-    s_i[tid] = bi;
+    for (int off = 32; off > 0; off >>= 1) better(best, bi, __shfl_xor(best, off), __shfl_xor(bi, off));
+    if (lane == 0) { s_wv[wave] = best; s_wi[wave] = bi; }
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-      if (tid < h) {
-        const double v2 = s_v[tid + h];
-        const int i2 = s_i[tid + h];
-        if (v2 > s_v[tid] || (v2 == s_v[tid] && i2 < s_i[tid])) { s_v[tid] = v2; s_i[tid] = i2; }
-      }
-      __syncthreads();
+    best = s_wv[0];
+    bi = s_wi[0];
+    for (int w = 1; w < kCapWaves; ++w) better(best, bi, s_wv[w], s_wi[w]);
+    const int piv = bi;
+    if (!(best > 0.0) || !isfinite(best) || piv >= r) {
+      if (tid == 0) s_bad = 1;
+      break;  // uniform: every thread reduced the same values
     }
-    const int piv = s_i[0];
-    if (tid == 0 && (!(s_v[0] > 0.0) || !isfinite(s_v[0]) || piv >= r)) s_bad = 1;
-    __syncthreads();
-    if (s_bad) break;
-    // swap rows k and piv of both halves
-    if (piv != k) {
-      for (int j = tid; j < R; j += 256) {
+    // swap rows k and piv, then the pivot row scaled (its column k becomes 1/pivot) and
+    // the other rows' column k, read before any row changes
+    if (piv != k)
+      for (int j = tid; j < r; j += kCapThreads) {
         const double2 t0 = A[(int64_t)k * R + j];
         A[(int64_t)k * R + j] = A[(int64_t)piv * R + j];
         A[(int64_t)piv * R + j] = t0;
-        const double2 t1 = Cm[(int64_t)k * R + j];
-        Cm[(int64_t)k * R + j] = Cm[(int64_t)piv * R + j];
-        Cm[(int64_t)piv * R + j] = t1;
       }
-      __syncthreads();
-    }
-    // scale the pivot row, then eliminate column k from every other row; the factors of
-    // column k are read before any row changes
+    __syncthreads();
     const double2 inv = crecip(A[(int64_t)k * R + k]);
-    __syncthreads();
-    for (int j = tid; j < R; j += 256) {
-      A[(int64_t)k * R + j] = cmul(A[(int64_t)k * R + j], inv);
-      Cm[(int64_t)k * R + j] = cmul(Cm[(int64_t)k * R + j], inv);
+    for (int j = tid; j < r; j += kCapThreads) {
+      const double2 v = j == k ? inv : cmul(A[(int64_t)k * R + j], inv);
+      s_row[j] = v;
+      s_col[j] = j == k ? make_double2(0.0, 0.0) : A[(int64_t)j * R + k];
     }
-    for (int i = tid; i < r; i += 256) s_f[i] = i == k ? make_double2(0.0, 0.0) : A[(int64_t)i * R + k];
+    if (tid == 0) s_perm[k] = piv;
     __syncthreads();
-    for (int64_t e = tid; e < (int64_t)r * R; e += 256) {
-      const int i = (int)(e / R), j = (int)(e % R);
+    for (int j = tid; j < r; j += kCapThreads) A[(int64_t)k * R + j] = s_row[j];
+    for (int64_t e = tid; e < (int64_t)r * r; e += kCapThreads) {
+      const int i = (int)(e / r), j = (int)(e - (e / r) * r);
       if (i == k) continue;
-      const double2 f = s_f[i];
-      A[(int64_t)i * R + j] = cfms(A[(int64_t)i * R + j], f, A[(int64_t)k * R + j]);
-      Cm[(int64_t)i * R + j] = cfms(Cm[(int64_t)i * R + j], f, Cm[(int64_t)k * R + j]);
+      const double2 a = j == k ? make_double2(0.0, 0.0) : A[(int64_t)i * R + j];
+      A[(int64_t)i * R + j] = cfms(a, s_col[i], s_row[j]);
     }
     __syncthreads();
+  }
+  if (k == r) {
+    // undo the row interchanges on the columns, last first (one thread per row)
+    for (int i = tid; i < r; i += kCapThreads)
+      for (int kk = r - 1; kk >= 0; --kk) {
+        const int p = s_perm[kk];
+        if (p != kk) {
+          const double2 t0 = A[(int64_t)i * R + kk];
+          A[(int64_t)i * R + kk] = A[(int64_t)i * R + p];
+          A[(int64_t)i * R + p] = t0;
+        }
+      }
+    __syncthreads();
+  }
+  for (int64_t e = tid; e < (int64_t)R * R; e += kCapThreads) {
+    const int i = (int)(e / R), j = (int)(e - (e / R) * R);
+    Cm[e] = (i < r && j < r) ? A[(int64_t)i * R + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (tid == 0 && s_bad) atomicMin(&c.status[b], kStatusSingular);
 }

@@ -10,7 +10,9 @@
 // from the parent's X (its update rows are rows of ancestors), -X_f[S] is stored in
 // R_f[S], and X_f[J] = [A_JJ^{-1} | U^] [R_f[J]; -X_f[S]] = A_JJ^{-1} R_J - U^ X_S.
 // The products are GEMM launches; the kernels here move rows between fronts.
-// One thread per (row, column) element; consecutive threads take consecutive columns.
+// One thread per (row, column) element; consecutive threads take consecutive elements of
+// the front block's storage: consecutive columns of a row (right solves) or consecutive
+// rows of a column (left solves).
 // Left solves (row vectors, W D = G) run the transposed recurrences with the same
 // factors: forward G_f[S] -= G_f[J] U^, backward W_J = G_J A_JJ^{-1} - W_S L^, on front
 // blocks stored n x H (TRANS).
@@ -32,6 +34,12 @@ __device__ __forceinline__ int find_desc(const Desc* d, int n, int64_t blk) {
 
 // Element (row I, right-hand side j) of a front block of H rows: row-major H x ns for
 // right solves, ns x H (TRANS) for left solves.
+// Thread element e of an n x ns block, in the block's storage order.
+template <bool TRANS>
+__device__ __forceinline__ void elem_rc(int64_t e, int n, int ns, int& row, int& col) {
+  if (TRANS) { col = (int)(e / n); row = (int)(e - (int64_t)col * n); }
+  else { row = (int)(e / ns); col = (int)(e - (int64_t)row * ns); }
+}
 template <bool TRANS>
 __device__ __forceinline__ int64_t rhs_at(int64_t off, int I, int j, int H, int ns) {
   return TRANS ? off + (int64_t)j * H + I : off + (int64_t)I * ns + j;
@@ -47,7 +55,8 @@ k_rhs_assemble(const RhsAsmDesc* __restrict__ descs, int ndesc, double2* __restr
   const RhsAsmDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.H * ns) return;
-  const int I = (int)(e / ns), col = (int)(e - (e / ns) * ns);
+  int I, col;
+  elem_rc<TRANS>(e, d.H, ns, I, col);
   if (lim && col >= lim[cfg * lim_stride]) return;  // past the live right-hand sides
   double2* R = rhs + cfg * rhs_stride;
   double2 v = make_double2(0.0, 0.0);
@@ -74,7 +83,8 @@ k_rhs_gather(const RhsGatherDesc* __restrict__ descs, int ndesc, double2* __rest
   const RhsGatherDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.s * ns) return;
-  const int r = (int)(e / ns), col = (int)(e - (e / ns) * ns);
+  int r, col;
+  elem_rc<TRANS>(e, d.s, ns, r, col);
   if (lim && col >= lim[cfg * lim_stride]) return;
   double2* R = rhs + cfg * rhs_stride;
   const int H = d.p + d.s;
@@ -94,7 +104,8 @@ k_sol_scatter(const SolScatterDesc* __restrict__ descs, int ndesc, const double2
   const SolScatterDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.p * ns) return;
-  const int I = (int)(e / ns), col = (int)(e - (e / ns) * ns);
+  int I, col;
+  elem_rc<TRANS>(e, d.p, ns, I, col);
   const int site = front_sites[d.site_off + I / 3];
   double2* dst = x + cfg * x_stride + ((int64_t)site * 3 + I % 3) * ns + col;
   if (lim && col >= lim[cfg * lim_stride]) {  // the solution of a zero right-hand side

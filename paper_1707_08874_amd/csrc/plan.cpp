@@ -119,8 +119,9 @@ int build_plan(const int32_t dims[4], const PlanOptions& opt, Plan& P, std::stri
     err = "invalid plan options";
     return -1;
   }
-  if (opt.lowrank_cap < 0 || opt.lowrank_cap > 1024 || !(opt.pivot_floor == opt.pivot_floor)) {
-    err = "invalid plan options (lowrank_cap must be 0..1024, pivot_floor a number)";
+  if (opt.lowrank_cap < 0 || opt.lowrank_cap > 1024 || !(opt.pivot_floor == opt.pivot_floor) ||
+      opt.smw_refine < 0 || opt.smw_refine > 1) {
+    err = "invalid plan options (lowrank_cap must be 0..1024, pivot_floor a number, smw_refine 0 or 1)";
     return -1;
   }
   P = Plan();

@@ -30,6 +30,9 @@ struct PlanOptions {
   // configuration. pivot_floor < 0: no perturbation, pivoting inside supernodes only.
   double pivot_floor = 0.3;
   int lowrank_cap = 0;      // 0: default_lowrank_cap(N)
+  // refinement steps (0 or 1) of the correction's right and left solves against D~ formed
+  // from the links: measured to leave the selected blocks' accuracy unchanged, so off
+  int smw_refine = 0;
 };
 
 // Default number of perturbed pivots one configuration can have undone: 64 per 24576

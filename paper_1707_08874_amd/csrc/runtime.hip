@@ -450,6 +450,7 @@ int cl_symbolic_ex(const int32_t dims[4], const cl_plan_opts* opts, cl_plan* out
     o.gemm_tile = opts->gemm_tile;
     if (opts->lowrank_cap != 0) o.lowrank_cap = opts->lowrank_cap;
     if (opts->pivot_floor != 0.0) o.pivot_floor = opts->pivot_floor;
+    o.smw_refine = opts->smw_refine;
   }
   if (o.gemm_tile != 0 && o.gemm_tile != clsel::kTile64 && o.gemm_tile != clsel::kTile128x64 &&
       o.gemm_tile != clsel::kTile128)
@@ -489,6 +490,7 @@ int cl_plan_info(cl_plan plan, cl_plan_info_t* o) {
   o->flops_dense_inverse = P.flops_dense_inverse;
   o->lowrank_cap = P.opt.lowrank_cap;
   o->pivot_floor = P.opt.pivot_floor;
+  o->smw_refine = P.opt.smw_refine;
   return 0;
 }
 
@@ -834,8 +836,9 @@ clsel::SmwCtx smw_ctx(cl_batch b) {
 }
 
 // The low-rank correction of the perturbed pivots, after the selected blocks of D~ are
-// gathered (see k_smw.hip): X and Y^T by right and left solves with one refinement step
-// each, C = (I + V^T X)^{-1}, X C, and the blocks corrected in place.
+// gathered (see k_smw.hip): X and Y^T by right and left solves (with the plan's
+// smw_refine, one refinement step each), C = (I + V^T X)^{-1}, X C, and the blocks
+// corrected in place.
 int enqueue_smw(cl_batch b) {
   const clsel::Plan& P = b->plan->P;
   const Layout& L = b->L;
@@ -857,8 +860,8 @@ int enqueue_smw(cl_batch b) {
   hipLaunchKernelGGL(clsel::k_smw_rhs, g_nr, dim3(256), 0, b->st, c, 1);
   HIPCHK(hipGetLastError());
   if ((rc = run_solve(b, b->smw_l, b->smw_blob_l, b->smw_rhs, rbuf, wst, Yt, wst, 0))) return rc;
-  // one refinement step each: residual against D~ = D + perturbations, solve, add
-  for (int trans = 0; trans < 2; ++trans) {
+  // optionally one refinement step each: residual against D~ = D + perturbations, solve, add
+  for (int trans = 0; trans < 2 * P.opt.smw_refine; ++trans) {
     hipLaunchKernelGGL(clsel::k_smw_residual, g_vr, dim3(256), 0, b->st, c, b->links, b->linv, b->params,
                        b->params + b->cap, ldims(P), P.V, trans);
     HIPCHK(hipGetLastError());
@@ -868,7 +871,7 @@ int enqueue_smw(cl_batch b) {
                         rbuf, wst, trans ? Yt : X, wst, 1)))
       return rc;
   }
-  hipLaunchKernelGGL(clsel::k_smw_capacitance, dim3(B), dim3(256), 0, b->st, c);
+  hipLaunchKernelGGL(clsel::k_smw_capacitance, dim3(B), dim3(1024), 0, b->st, c);
   HIPCHK(hipGetLastError());
   clsel::launch_gemm(0, L.smw_xc.tile, dim3((unsigned)L.smw_xc.gridx, (unsigned)B), b->st,
                      (const clsel::GemmDesc*)(b->dblob + L.smw_xc.desc_off), L.smw_xc.count, b->fronts,
