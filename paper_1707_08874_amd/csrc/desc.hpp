@@ -68,7 +68,8 @@ struct GemmDesc {
   // alias A, B or C0); 0: one chain of products over all of K
   int kblock;
   // solve launches: 1 (M) or 2 (N) is the right-hand-side extent, cut per configuration
-  // to its live count; 0: none
+  // to its live count; 3: N and K are both cut (X C with C = the inverse of the live
+  // block bordered by the identity, X zero past the live columns); 0: none
   int lim_dim;
   // has_c0 = 2 (Schur complement S = A_SS - A_SJ U^): A_SS is the sum over the children
   // of their update blocks at the mapped positions, read here instead of from an

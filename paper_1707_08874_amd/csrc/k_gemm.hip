@@ -74,9 +74,9 @@ struct Operands {
 
 template <int MODE, int RA>
 __device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE, RA>& o, int r, int t,
-                                       int Mv) {
+                                       int Mv, int Kv) {
   const double2 z = make_double2(0.0, 0.0);
-  if (t >= d.K || o.ai[r] >= Mv) return z;
+  if (t >= Kv || o.ai[r] >= Mv) return z;
   if (MODE == 2) {
     const int i = o.ai[r] + d.row_base;
     if (i >= d.k && i < d.k + d.nbk) return make_double2(i - d.k == t ? -1.0 : 0.0, 0.0);
@@ -114,11 +114,12 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   // the product's extent; in the solves the right-hand sides past this configuration's
   // live count are neither read nor written (their columns or rows of the result stay
   // as they were; the kernels that read them skip them too)
-  int Mv = d.M, Nv = d.N;
+  int Mv = d.M, Nv = d.N, Kv = d.K;
   if constexpr (SOLVE) {
     if (d.lim_dim) {
       const int c = g.lim[b * g.lim_stride];
       if (d.lim_dim == 1) Mv = min(Mv, c); else Nv = min(Nv, c);
+      if (d.lim_dim == 3) Kv = min(Kv, c);
       if (row0 >= Mv || col0 >= Nv) return;  // uniform over the work-group
     }
   }
@@ -162,7 +163,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   auto ld_b = [&](int t) __attribute__((always_inline)) -> double2 {
     const double2 z = make_double2(0.0, 0.0);
     const int j = bcol;
-    if (t >= d.K || j >= Nv) return z;
+    if (t >= Kv || j >= Nv) return z;
     if (MODE == 0) return o.bbase[(int64_t)t * d.ldb + j];
     if (MODE == 1) {
       if (j >= d.k && j < d.k + d.nbk) return make_double2(j - d.k == t ? 1.0 : 0.0, 0.0);
@@ -215,7 +216,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 
   auto load_stage = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk, Mv);
+    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk, Mv, Kv);
 #pragma unroll
     for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + b_kk0 + b_kstep * r);
   };
@@ -306,7 +307,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     }
   };
 
-  const int nst = (d.K + BK - 1) / BK;
+  const int nst = (Kv + BK - 1) / BK;
   // Blocked summation (mode 0, d.kblock): the accumulators hold the sum over one chunk of
   // kKChunk products; at the end of each chunk but the last, it is added to the running
   // total, which waits in C (each lane reads and writes only its own outputs), and the

@@ -287,6 +287,7 @@ void build_layout(const clsel::Plan& P, Layout& L) {
     d.b_pool = clsel::kPoolWs; d.b_off = L.c_off; d.ldb = R;
     d.c_pool = clsel::kPoolWs; d.c_off = L.xc_off; d.ldc = R;
     d.alpha = 1.0; d.has_c0 = 0; d.kblock = 0;
+    d.lim_dim = 3;  // columns and sums past the configuration's count are skipped
     L.smw_xc = gemm_launch(L.blob, g, 0, clsel::kTile64);
   }
   for (std::vector<Launch>* ls : {&L.factor, &L.selinv})

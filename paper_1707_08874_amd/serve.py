@@ -10,7 +10,10 @@ soon as it finishes, so requests that arrive while others are running are admitt
 as slots and memory free up. Idle slots of other shapes are released when a new
 slot does not fit the budget. Every configuration in a batch is computed
 independently, so a result does not depend on what it was batched with (the tests
-check this bit for bit).
+check this bit for bit). A request whose configuration has more perturbed pivots than
+its plan's low-rank correction holds (CL_ERANK: the count depends on m, mu and the
+links) is run again with a wide plan of the same shape, whose correction holds the
+library's maximum; its result is then that of the wide plan.
 
     python -m paper_1707_08874_amd.serve --requests 200 --rate 30
 """
@@ -29,6 +32,7 @@ from . import autotune, clsel
 from .inputs import gen_links, volume
 
 DEFAULT_MIX = (((4, 4, 4, 4), 0.3), ((6, 6, 6, 6), 0.3), ((8, 8, 8, 4), 0.3), ((12, 12, 12, 6), 0.1))
+WIDE_LOWRANK_CAP = 1024  # the library's largest low-rank correction
 
 
 @dataclass
@@ -46,6 +50,7 @@ class Request:
     status: int = 0
     batch_size: int = 0
     slot_id: int = -1
+    wide: bool = False            # run with the shape's wide plan (after CL_ERANK)
     dev_start_ms: float = -1.0    # device time of the launch's start and end (HIP events on
     dev_end_ms: float = -1.0      # its slot stream), in ms after the run's reference event
 
@@ -56,7 +61,7 @@ class Request:
 
 @dataclass
 class _Slot:
-    dims: tuple
+    key: tuple                    # (dims, wide)
     capacity: int
     batch: clsel.Batch
     stream: object
@@ -103,31 +108,42 @@ class Server:
         self.ref_event = None  # device-time origin of the current run
 
     # ---------------------------------------------------------------- plans and slots
-    def plan(self, dims) -> clsel.Plan:
-        dims = tuple(int(v) for v in dims)
-        if dims not in self.plans:
+    @staticmethod
+    def key(dims, wide: bool = False) -> tuple:
+        """Plan key: the lattice shape and whether the plan is the wide one."""
+        return tuple(int(v) for v in dims), bool(wide)
+
+    def plan(self, key) -> clsel.Plan:
+        """The plan of a key (dims, wide); a bare shape means its regular plan."""
+        if len(key) == 4:
+            key = self.key(key)
+        if key not in self.plans:
+            dims, wide = key
             opts = self.plan_opts.get(dims)
             if opts is None:
                 opts = autotune.options(dims, 1)
-            self.plans[dims] = clsel.Plan(dims, **opts)
-        return self.plans[dims]
+            if wide:
+                opts = dict(opts, lowrank_cap=WIDE_LOWRANK_CAP)
+            self.plans[key] = clsel.Plan(dims, **opts)
+        return self.plans[key]
 
-    def capacity(self, dims) -> int:
-        per = self.plan(dims).bytes(1)
+    def capacity(self, key) -> int:
+        per = self.plan(key).bytes(1)
         return int(max(1, min(self.max_capacity, self.slot_bytes_target // max(per, 1))))
 
-    def _slot_bytes(self, dims, cap) -> int:
-        V = volume(dims)
+    def _slot_bytes(self, key, cap) -> int:
+        V = volume(key[0])
         io = cap * V * 16 * (36 + (81 if self.keep_selected else 0) + 32)
-        return self.plan(dims).bytes(cap) + io
+        return self.plan(key).bytes(cap) + io
 
-    def _new_slot(self, dims) -> _Slot | None:
+    def _new_slot(self, key) -> _Slot | None:
         torch = self.torch
-        cap = self.capacity(dims)
-        need = self._slot_bytes(dims, cap)
+        dims = key[0]
+        cap = self.capacity(key)
+        need = self._slot_bytes(key, cap)
         if need > self.budget:
             cap = 1
-            need = self._slot_bytes(dims, 1)
+            need = self._slot_bytes(key, 1)
             if need > self.budget:
                 raise clsel.ClselError(clsel.CL_ENOMEM, f"one {dims} configuration needs {need} B, "
                                                         f"above the HBM budget {self.budget} B")
@@ -137,9 +153,9 @@ class Server:
             return None
         V = volume(dims)
         stream = torch.cuda.Stream()
-        batch = clsel.Batch(self.plan(dims), cap, stream=stream)
+        batch = clsel.Batch(self.plan(key), cap, stream=stream)
         dev = dict(dtype=torch.complex128, device="cuda")
-        slot = _Slot(dims=dims, capacity=cap, batch=batch, stream=stream,
+        slot = _Slot(key=key, capacity=cap, batch=batch, stream=stream,
                      links=torch.empty((cap, V, 4, 3, 3), **dev),
                      sel=torch.empty((cap, V, 9, 3, 3), **dev) if self.keep_selected else None,
                      drift=torch.empty((cap, V, 4, 8), **dev),
@@ -149,14 +165,14 @@ class Server:
                      host_drift=torch.empty((cap, V, 4, 8), dtype=torch.complex128, pin_memory=True),
                      nbytes=need, sid=self.nslots)
         self.nslots += 1
-        self.slots[dims].append(slot)
+        self.slots[key].append(slot)
         self.used += need
         self.peak_used = max(self.peak_used, self.used)
         return slot
 
     def _free_slot(self, slot: _Slot):
         slot.batch.close()
-        self.slots[slot.dims].remove(slot)
+        self.slots[slot.key].remove(slot)
         self.used -= slot.nbytes
         del slot
         self.torch.cuda.empty_cache()
@@ -174,14 +190,14 @@ class Server:
         """Plans and one idle slot per shape, so that a measured stream does not pay for
         the symbolic analysis or the first device allocations."""
         for d in shapes:
-            d = tuple(int(v) for v in d)
-            self.plan(d)
-            if not self.slots[d]:
-                self._new_slot(d)
+            k = self.key(d)
+            self.plan(k)
+            if not self.slots[k]:
+                self._new_slot(k)
 
     # ---------------------------------------------------------------- request flow
     def submit(self, req: Request):
-        self.queues[tuple(req.dims)].append(req)
+        self.queues[self.key(req.dims, req.wide)].append(req)
 
     def _launch(self, slot: _Slot, reqs: list[Request]):
         torch = self.torch
@@ -219,10 +235,14 @@ class Server:
         for i, r in enumerate(slot.reqs):
             r.slot_id = slot.sid
             r.dev_start_ms, r.dev_end_ms = t_start, t_end
+            r.status = int(st[i])
+            if r.status == clsel.CL_ERANK and not r.wide:
+                r.wide = True  # more perturbed pivots than the plan holds: the wide plan
+                self.submit(r)
+                continue
             if slot.host_sel is not None:
                 r.selected = slot.host_sel[i].numpy().copy()
             r.drift = slot.host_drift[i].numpy().copy()
-            r.status = int(st[i])
             r.t_done = now
             self.done.append(r)
         slot.reqs = []
@@ -240,11 +260,11 @@ class Server:
                 if s.busy and s.event.query():
                     self._finish(s)
                     progressed = True
-        for dims, q in self.queues.items():
+        for key, q in list(self.queues.items()):
             while q:
-                slot = next((s for s in self.slots[dims] if not s.busy), None)
-                if slot is None and len(self.slots[dims]) < self.max_slots_per_shape:
-                    slot = self._new_slot(dims)
+                slot = next((s for s in self.slots[key] if not s.busy), None)
+                if slot is None and len(self.slots[key]) < self.max_slots_per_shape:
+                    slot = self._new_slot(key)
                 if slot is None:
                     break
                 take = [q.popleft() for _ in range(min(slot.capacity, len(q)))]
@@ -349,6 +369,7 @@ def summarize(reqs: list[Request], wall: float) -> dict:
         "p90_ms": float(np.percentile(lat, 90) * 1e3),
         "p99_ms": float(np.percentile(lat, 99) * 1e3),
         "mean_batch": float(np.mean([r.batch_size for r in reqs])),
+        "wide_reruns": int(sum(r.wide for r in reqs)),
         "device_overlap": device_overlap(reqs),
         "by_shape": per_shape,
         "failed": int(sum(r.status != 0 for r in reqs)),

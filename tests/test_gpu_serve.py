@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from paper_1707_08874_amd import autotune, clsel
-from paper_1707_08874_amd.serve import Server, device_overlap, make_requests
+from paper_1707_08874_amd.serve import WIDE_LOWRANK_CAP, Server, device_overlap, make_requests
 from parity import TOL, assert_parity
 
 pytestmark = pytest.mark.gpu
@@ -22,8 +22,11 @@ def torch_cuda():
     return torch
 
 
-def _alone(torch, r):
-    plan = clsel.Plan(r.dims, **autotune.options(r.dims, 1))  # the server's plan options
+def _alone(torch, r, opts=None):
+    opts = dict(autotune.options(r.dims, 1) if opts is None else opts)  # the server's plan options
+    if r.wide:
+        opts["lowrank_cap"] = WIDE_LOWRANK_CAP
+    plan = clsel.Plan(r.dims, **opts)
     b = clsel.Batch(plan, 1)
     lt = torch.from_numpy(r.links[None].copy()).to("cuda")
     sel, drift = b.run(lt, [r.m], [r.mu])
@@ -95,3 +98,26 @@ def test_real_mix_overlaps_on_device_and_equals_alone(torch_cuda):
         ref = oracle.selected_blocks(Z, r.dims)
         assert_parity(r.selected, r.drift, ref, oracle.drift_from_blocks(ref, r.links, r.dims, r.mu),
                       TOL, label=str(dims))
+
+
+def test_requests_over_the_lowrank_cap_rerun_with_the_wide_plan(torch_cuda):
+    """A plan whose correction holds a single perturbed pivot: configurations with more
+    get CL_ERANK, and the server runs them again with the shape's wide plan. Every request
+    completes with status 0, the reruns are marked, and their results are those of the
+    wide plan run alone (bit for bit) and match the oracle."""
+    opts = {"lowrank_cap": 1}
+    reqs = make_requests(8, rate=1e6, seed=6, mix=(((4, 4, 4, 4), 1.0),), pool=4)
+    srv = Server(hbm_budget=int(4e9), slot_bytes_target=1e12, max_capacity=4,
+                 plan_opts={(4, 4, 4, 4): opts})
+    done = srv.run(reqs)
+    srv.close()
+    assert len(done) == 8 and all(r.status == 0 for r in done)
+    wide = [r for r in done if r.wide]
+    assert wide, "some configuration should have had more than one perturbed pivot"
+    for r in wide[:2] + [r for r in done if not r.wide][:1]:
+        s1, d1 = _alone(torch_cuda, r, opts)
+        assert np.array_equal(r.selected, s1) and np.array_equal(r.drift, d1), r.rid
+    r = wide[0]
+    Z = oracle.inverse_dense(oracle.dirac_dense(r.links, r.dims, r.m, r.mu))
+    ref = oracle.selected_blocks(Z, r.dims)
+    assert_parity(r.selected, r.drift, ref, oracle.drift_from_blocks(ref, r.links, r.dims, r.mu), TOL)
