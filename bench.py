@@ -105,6 +105,9 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-burst", type=int, default=300)
+    ap.add_argument("--gap-phases", action="store_true",
+                    help="for a kernel trace: the plain path (graph replay, then eager) and the "
+                         "batched step (graph replay), each phase after a 0.3 s pause")
     ap.add_argument("--lanes", type=int, default=0,
                     help="lanes of the batched step (0: automatic, 1, or 2 streams)")
     ap.add_argument("--pivot-floor", type=float, default=0.0,
@@ -138,6 +141,8 @@ def main():
         return parity_sweep(args)
     if args.serve:
         return serve(args)
+    if args.gap_phases:
+        return gap_phases(args)
 
     dims, m, mu, B = (8, 8, 8, 4), 0.05, 0.25, args.batch
     if args.calibrate_copy:
@@ -335,7 +340,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"batched: {B} x 8^3x4 lattices (N=6144 each), seeds 0..{B - 1}, "
                                "eps~U[0.02,0.3], m=0.05, mu=0.25, one shared symbolic analysis",
-                   "lattice": "8x8x8x4", "batch": B, "plan_batched": opts_b, "plan_plain": opts_1},
+                   "lattice": "8x8x8x4", "batch": B, "plan_batched": opts_b, "plan_plain": opts_1,
+                   "lanes": args.lanes or (2 if B >= 16 else 1)},
         "plain": plain,
         "batched_over_plain": value / plain["value"] if plain else None,
         "path_tflops_alg": alg_flops * B * args.steps / dt / 1e12,
@@ -648,6 +654,41 @@ def langevin(args):
            "eps_used_range": [float(np.min(eps_used)), float(np.max(eps_used))],
            "status_ok": bool((st == 0).all())}
     print(json.dumps(out))
+
+
+def gap_phases(args):
+    """Phases separated by idle pauses, for ``rocprofv3 --kernel-trace`` and
+    ``profsum gaps``: (0) plain path, graph replay, warm-up; (1) 10 plain runs, graph
+    replay; (2) 5 plain runs, eager; (3) batched step warm-up; (4) 3 batched steps, graph
+    replay. The idle fraction of a phase is the launch gap between its kernels."""
+    import numpy as np
+    import torch
+
+    from paper_1707_08874_amd import autotune, clsel
+    from paper_1707_08874_amd.inputs import gen_batch
+    dims, m, mu = (8, 8, 8, 4), 0.05, 0.25
+
+    def phase(B, runs, graph, label):
+        plan = clsel.Plan(dims, **autotune.options(dims, B))
+        lt = torch.from_numpy(gen_batch(dims, range(B))).to("cuda")
+        b = clsel.Batch(plan, B)
+        b.use_graph(graph)
+        sel, drift = b.run(lt, m, mu)
+        b.sync()
+        time.sleep(0.3)
+        t = []
+        for _ in range(runs):
+            a = time.perf_counter()
+            b.run(lt, m, mu, sel, drift)
+            b.sync()
+            t.append(time.perf_counter() - a)
+        print(f"[gaps] {label}: {runs} runs, median {np.median(t) * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        b.close()
+        time.sleep(0.3)
+
+    phase(1, 10, True, "plain, graph replay")
+    phase(1, 5, False, "plain, eager")
+    phase(args.batch, 3, True, f"batched {args.batch}, graph replay")
 
 
 def serve(args):

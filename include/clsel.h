@@ -67,7 +67,7 @@ typedef struct {
   int32_t time_cuts;      /* 1: separators may cut the time direction; 0 (default): never */
   int32_t gemm_tile;      /* output tile of the plain products: 0 auto (64 x 64), 64, 12864, 128 */
   int32_t lowrank_cap;    /* perturbed pivots one configuration may have undone (0: default,
-                             64 per 24576 rows of D, at least 64; at most 1024) */
+                             64 per 24576 rows of D, at least 128; at most 1024) */
   double pivot_floor;     /* pivot perturbation threshold in units of D's entries (0: default 0.3;
                              negative: no perturbation). See cl_factor. */
   int32_t smw_refine;     /* 1: one refinement step of the correction's solves against D~

@@ -36,12 +36,14 @@ struct PlanOptions {
 };
 
 // Default number of perturbed pivots one configuration can have undone: 64 per 24576
-// matrix rows (8192 sites), at least 64. Measured counts at the default floor: 0 to 26
-// on 8^3x4 configurations, 31 on a 12^3x6 one; most come from the leaf supernodes, whose
-// number grows with the volume.
+// matrix rows (8192 sites), at least 128. Measured counts at the default floor 0.3: up to
+// 33 on 8^3x4 configurations at m = 0.05, mu = 0.25, and up to 54 at m = 0.02, mu = 0 (the
+// count grows as m and mu fall); 31 on a 12^3x6 one. Most come from the leaf supernodes,
+// whose number grows with the volume. The correction's work follows the actual count; the
+// cap sizes its buffers.
 inline int default_lowrank_cap(int64_t n) {
   const int64_t c = 64 * ((n + 24575) / 24576);
-  return (int)(c < 64 ? 64 : (c > 1024 ? 1024 : c));
+  return (int)(c < 128 ? 128 : (c > 1024 ? 1024 : c));
 }
 
 struct Front {

@@ -6,6 +6,13 @@ Two jobs, both on the CSV files rocprofv3 writes with ``--output-format csv``:
     per-kernel dispatch statistics from ``*kernel_trace.csv``, split by the batch
     (grid y), printed as markdown tables.
 
+``gaps DIR``
+    launch gaps: the trace's dispatches split into phases wherever the device is idle
+    for more than ``--idle-ms`` (bench.py ``--gap-phases`` separates its phases by
+    sleeps); per phase the wall time from the first start to the last end, the sum of
+    kernel durations, the time the device had a kernel running (union of intervals)
+    and the idle fraction 1 - busy / wall, with the kernels that took the most time.
+
 ``traffic --fetch DIR --write DIR ...``
     HBM traffic per launch of one kernel from two ``--pmc`` passes (``FETCH_SIZE``,
     then ``WRITE_SIZE``, both in KiB per dispatch). Each counter is scaled by what it
@@ -86,6 +93,48 @@ def stats_markdown(directory: str) -> str:
     return "\n".join(lines)
 
 
+def gap_phases(directory: str, idle_ms: float = 50.0):
+    """Phases of the kernel trace: lists of (start_ns, end_ns, kernel) split where no
+    kernel runs for more than idle_ms."""
+    ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+                for r in _rows(directory, "kernel_trace.csv"))
+    phases, last_end = [], None
+    for k in ks:
+        if last_end is None or k[0] - last_end > idle_ms * 1e6:
+            phases.append([])
+        phases[-1].append(k)
+        last_end = k[1] if last_end is None else max(last_end, k[1])
+    return phases
+
+
+def gaps_markdown(directory: str, idle_ms: float = 50.0, top: int = 8) -> str:
+    lines = ["| phase | dispatches | wall ms | kernel sum ms | busy ms | idle fraction |",
+             "|---|---|---|---|---|---|"]
+    details = []
+    for i, ph in enumerate(gap_phases(directory, idle_ms)):
+        t0, t1 = ph[0][0], max(e for _, e, _ in ph)
+        busy, cs, ce = 0, None, None
+        for b, e, _ in ph:
+            if ce is None or b > ce:
+                if ce is not None:
+                    busy += ce - cs
+                cs, ce = b, e
+            else:
+                ce = max(ce, e)
+        busy += ce - cs
+        ksum = sum(e - b for b, e, _ in ph)
+        lines.append(f"| {i} | {len(ph)} | {(t1 - t0) * 1e-6:.2f} | {ksum * 1e-6:.2f} | {busy * 1e-6:.2f} | "
+                     f"{1 - busy / max(t1 - t0, 1):.4f} |")
+        agg = defaultdict(lambda: [0, 0])
+        for b, e, n in ph:
+            agg[n][0] += 1
+            agg[n][1] += e - b
+        details += ["", f"Phase {i}: kernels by time", "", "| kernel | dispatches | ms | share |", "|---|---|---|---|"]
+        for n, (c, t) in sorted(agg.items(), key=lambda x: -x[1][1])[:top]:
+            details.append(f"| {n} | {c} | {t * 1e-6:.2f} | {100 * t / max(ksum, 1):.1f}% |")
+    return "\n".join(lines + details)
+
+
 def counter_per_dispatch(directory: str, counter: str, pattern: str):
     """Values of one counter for every dispatch whose kernel name matches the pattern."""
     rx = re.compile(pattern)
@@ -128,6 +177,9 @@ def main(argv=None):
     sub = ap.add_subparsers(dest="cmd", required=True)
     s = sub.add_parser("stats")
     s.add_argument("dir")
+    gp = sub.add_parser("gaps")
+    gp.add_argument("dir")
+    gp.add_argument("--idle-ms", type=float, default=50.0)
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -144,6 +196,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         print(stats_markdown(a.dir))
+        return 0
+    if a.cmd == "gaps":
+        print(gaps_markdown(a.dir, a.idle_ms))
         return 0
     rec = traffic_record(a.fetch, a.write, a.kernel, a.copy_kernel, a.copy_bytes)
     rec["workload"] = a.workload
