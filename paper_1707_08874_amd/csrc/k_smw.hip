@@ -178,7 +178,8 @@ __global__ void __launch_bounds__(256) k_smw_residual_delta(SmwCtx c, int trans)
 // scaled, every other row eliminated, and the column of the inverse kept where the
 // eliminated column was; the row interchanges are undone on the columns at the end, in
 // reverse order. One work-group of kCapThreads per configuration; the pivot row and column
-// of each step go through LDS, the elements stay in global memory (coalesced along rows).
+// of each step go through LDS, the elements stay in global memory: wave w takes rows
+// w, w + kCapWaves, ..., its lanes consecutive columns.
 constexpr int kCapThreads = 1024;
 constexpr int kCapWaves = kCapThreads / 64;
 
@@ -200,11 +201,13 @@ __global__ void __launch_bounds__(kCapThreads) k_smw_capacitance(SmwCtx c) {
   __shared__ double s_wv[kCapWaves];
   __shared__ int s_wi[kCapWaves];
   __shared__ int s_bad;
-  for (int64_t e = tid; e < (int64_t)r * r; e += kCapThreads) {
-    const int i = (int)(e / r), j = (int)(e - (e / r) * r);
-    double2 a = W[c.x_off + (int64_t)IW[c.lj_off + i] * R + j];
-    if (i == j) a = cadd(a, make_double2(1.0, 0.0));
-    A[(int64_t)i * R + j] = a;
+  for (int i = wave; i < r; i += kCapWaves) {
+    const double2* xr = W + c.x_off + (int64_t)IW[c.lj_off + i] * R;
+    for (int j = lane; j < r; j += 64) {
+      double2 a = xr[j];
+      if (i == j) a = cadd(a, make_double2(1.0, 0.0));
+      A[(int64_t)i * R + j] = a;
+    }
   }
   if (tid == 0) s_bad = 0;
   __syncthreads();
@@ -247,11 +250,14 @@ __global__ void __launch_bounds__(kCapThreads) k_smw_capacitance(SmwCtx c) {
     if (tid == 0) s_perm[k] = piv;
     __syncthreads();
     for (int j = tid; j < r; j += kCapThreads) A[(int64_t)k * R + j] = s_row[j];
-    for (int64_t e = tid; e < (int64_t)r * r; e += kCapThreads) {
-      const int i = (int)(e / r), j = (int)(e - (e / r) * r);
+    for (int i = wave; i < r; i += kCapWaves) {
       if (i == k) continue;
-      const double2 a = j == k ? make_double2(0.0, 0.0) : A[(int64_t)i * R + j];
-      A[(int64_t)i * R + j] = cfms(a, s_col[i], s_row[j]);
+      double2* ar = A + (int64_t)i * R;
+      const double2 f = s_col[i];
+      for (int j = lane; j < r; j += 64) {
+        const double2 a = j == k ? make_double2(0.0, 0.0) : ar[j];
+        ar[j] = cfms(a, f, s_row[j]);
+      }
     }
     __syncthreads();
   }
@@ -268,10 +274,9 @@ __global__ void __launch_bounds__(kCapThreads) k_smw_capacitance(SmwCtx c) {
       }
     __syncthreads();
   }
-  for (int64_t e = tid; e < (int64_t)R * R; e += kCapThreads) {
-    const int i = (int)(e / R), j = (int)(e - (e / R) * R);
-    Cm[e] = (i < r && j < r) ? A[(int64_t)i * R + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
-  }
+  for (int i = wave; i < R; i += kCapWaves)
+    for (int j = lane; j < R; j += 64)
+      Cm[(int64_t)i * R + j] = (i < r && j < r) ? A[(int64_t)i * R + j] : make_double2(i == j ? 1.0 : 0.0, 0.0);
   if (tid == 0 && s_bad) atomicMin(&c.status[b], kStatusSingular);
 }
 

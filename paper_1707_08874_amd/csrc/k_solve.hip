@@ -35,10 +35,12 @@ __device__ __forceinline__ int find_desc(const Desc* d, int n, int64_t blk) {
 // Element (row I, right-hand side j) of a front block of H rows: row-major H x ns for
 // right solves, ns x H (TRANS) for left solves.
 // Thread element e of an n x ns block, in the block's storage order.
+// (A front block has fewer than 2^31 elements; the solve layout check refuses others.)
 template <bool TRANS>
 __device__ __forceinline__ void elem_rc(int64_t e, int n, int ns, int& row, int& col) {
-  if (TRANS) { col = (int)(e / n); row = (int)(e - (int64_t)col * n); }
-  else { row = (int)(e / ns); col = (int)(e - (int64_t)row * ns); }
+  const unsigned u = (unsigned)e;
+  if (TRANS) { col = (int)(u / (unsigned)n); row = (int)(u - (unsigned)col * (unsigned)n); }
+  else { row = (int)(u / (unsigned)ns); col = (int)(u - (unsigned)row * (unsigned)ns); }
 }
 template <bool TRANS>
 __device__ __forceinline__ int64_t rhs_at(int64_t off, int I, int j, int H, int ns) {
