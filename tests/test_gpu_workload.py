@@ -8,7 +8,7 @@ The path perturbs pivots below the plan's floor and undoes the perturbation exac
 a low-rank correction (cl_factor, cl_selinv). What remains is the rounding of double
 precision in the static elimination order. With the workload's tuned plan (pivot floor
 0.5, so the factorised matrix D~ has no pivot below 0.5 in modulus), 58 of the 64
-configurations are within 1e-10 on every block and every link's drift (47 with the
+configurations are within 1e-10 on every block and every link's drift (48 with the
 library's default floor 0.3). The others are listed below with their measured worst
 error; they are expected failures at 1e-10 and are held to 1e-9 as a regression floor. The oracle itself
 is accurate to 7e-12 to 2e-11 on these blocks (against a long-double selected inversion of
