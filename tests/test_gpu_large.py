@@ -85,9 +85,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 LARGE_FLOOR = 1e-9
 
 
-def test_generic_sampled_sites_match_oracle(results):
-    """Every block and link drift the oracle computed around the sampled sites: printed
-    against 1e-10 and held to the measured floor of this path on the large lattices."""
+def _sampled(results):
     dims = results["dims"]
     path = os.path.join(GOLDEN, "large_%s.json" % "x".join(map(str, dims)))
     if not os.path.exists(path):
@@ -107,6 +105,21 @@ def test_generic_sampled_sites_match_oracle(results):
           f"{np.median(be):.1e}; {len(de)} links: worst drift {de.max():.2e} (oracle residual "
           f"{g['residual']:.1e}); {int((be > TOL).sum())} blocks and {int((de > TOL).sum())} links "
           f"above 1e-10", flush=True)
+    return be, de
+
+
+@pytest.mark.xfail(strict=False, reason="measured above 1e-10 on some sampled blocks (3.0e-10 on 12^3x6, "
+                                        "4.9e-10 on 16^3x8): the double-precision floor of the static order")
+def test_generic_sampled_sites_within_1e_10(results):
+    """Every block and link drift the oracle computed around the sampled sites, at the bar."""
+    be, de = _sampled(results)
+    assert be.max() <= TOL and de.max() <= TOL
+
+
+def test_generic_sampled_sites_at_the_floor(results):
+    """The same blocks and drifts held to the measured floor of this path on the large
+    lattices, so that a change that makes them worse is caught."""
+    be, de = _sampled(results)
     assert be.max() <= LARGE_FLOOR and de.max() <= LARGE_FLOOR
 
 

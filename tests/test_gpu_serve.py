@@ -71,7 +71,7 @@ def test_real_mix_overlaps_on_device_and_equals_alone(torch_cuda):
     """4^4, 6^4 and 8^3x4 requests arriving together: slots of different shapes (and two
     slots of one shape) have device intervals, from HIP events recorded on their own
     streams, that intersect; every result equals the same request run alone, bit for
-    bit, and matches the oracle on the two smaller shapes."""
+    bit, and one request of each shape matches the oracle."""
     reqs = make_requests(24, rate=1e6, seed=5, mix=REAL_MIX, pool=3)
     shapes = sorted({r.dims for r in reqs})
     assert len(shapes) == 3, shapes
@@ -92,7 +92,7 @@ def test_real_mix_overlaps_on_device_and_equals_alone(torch_cuda):
         r = next(r for r in done if r.dims == dims)
         s1, d1 = _alone(torch_cuda, r)
         assert np.array_equal(r.selected, s1) and np.array_equal(r.drift, d1), (dims, r.rid)
-    for dims in ((4, 4, 4, 4), (6, 6, 6, 6)):
+    for dims in ((4, 4, 4, 4), (6, 6, 6, 6), (8, 8, 8, 4)):
         r = next(r for r in done if r.dims == dims)
         Z = oracle.inverse_dense(oracle.dirac_dense(r.links, r.dims, r.m, r.mu))
         ref = oracle.selected_blocks(Z, r.dims)

@@ -97,16 +97,21 @@ def _check(workload, c):
     return float(be.max()), float(de.max())
 
 
-@pytest.mark.parametrize("c", [c for c in range(B) if c not in ABOVE_1E10])
+_XFAIL = pytest.mark.xfail(strict=False, reason="measured above 1e-10: the double-precision rounding floor "
+                                                "of the static elimination order (see the module docstring)")
+
+
+@pytest.mark.parametrize("c", [pytest.param(c, marks=_XFAIL) if c in ABOVE_1E10 else c for c in range(B)])
 def test_configuration_within_1e_10(workload, c):
+    """Every configuration against the bar, 1e-10 on every block and every link's drift; the
+    configurations measured above it are expected failures."""
     be, de = _check(workload, c)
     assert be <= TOL and de <= TOL, (c, be, de)
 
 
 @pytest.mark.parametrize("c", sorted(ABOVE_1E10))
 def test_configuration_at_the_double_precision_floor(workload, c):
-    """Expected to miss 1e-10 (see the module docstring); held to the regression floor."""
+    """The expected failures above are held to a regression floor, so that a change that
+    makes them worse is caught."""
     be, de = _check(workload, c)
     assert be <= FLOOR and de <= FLOOR, (c, be, de)
-    if be <= TOL and de <= TOL:
-        print(f"[gpu] config {c} is now within 1e-10", flush=True)

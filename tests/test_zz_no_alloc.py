@@ -28,7 +28,7 @@ def _both(torch, dims, seeds):
     print(f"\n[gpu] no-alloc run {dims} B={len(seeds)}", flush=True)
     links = gen_batch(dims, seeds)
     lt = torch.from_numpy(links).to("cuda")
-    plan = clsel.Plan(dims)
+    plan = clsel.Plan(dims, lowrank_cap=64)  # the correction's buffers sized to fit the 128 MiB array
     s0, d0, st0 = clsel.run_noalloc(plan, lt, M, MU)
     torch.cuda.synchronize()
     b = clsel.Batch(plan, len(seeds))
