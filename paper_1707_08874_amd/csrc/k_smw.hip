@@ -281,18 +281,18 @@ __global__ void __launch_bounds__(kCapThreads) k_smw_capacitance(SmwCtx c) {
 }
 
 // Selected blocks of D from those of D~: Z_{x,y} -= sum_k (X C)_{x,k} Y^T_{y,k} for the nine
-// blocks of every site (slot order of k_gather_selected). A failed configuration gets NaN.
+// blocks of every site (slot order of k_gather_selected), one thread per block. A failed
+// configuration gets NaN.
 __global__ void __launch_bounds__(256)
 k_smw_correct(SmwCtx c, double2* __restrict__ sel, LatticeDims dims, int64_t V) {
   const int b = blockIdx.y;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= V * 81) return;
-  const int64_t x = e / 81;
-  const int q = (int)(e % 81);
-  const int slot = q / 9, i = (q % 9) / 3, j = q % 3;
-  double2* out = sel + (int64_t)b * V * 81 + e;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;  // (site, slot): one 3x3 block
+  if (e >= V * 9) return;
+  const int64_t x = e / 9;
+  const int slot = (int)(e % 9);
+  double2* out = sel + (int64_t)b * V * 81 + e * 9;
   if (c.status[b] != 0) {
-    *out = make_double2(__builtin_nan(""), __builtin_nan(""));
+    for (int q = 0; q < 9; ++q) out[q] = make_double2(__builtin_nan(""), __builtin_nan(""));
     return;
   }
   const int32_t* IW = c.iws + b * c.iws_stride;
@@ -305,11 +305,21 @@ k_smw_correct(SmwCtx c, double2* __restrict__ sel, LatticeDims dims, int64_t V) 
     cx[nu] = (cx[nu] + (slot <= 4 ? 1 : -1) + dims.L[nu]) % dims.L[nu];
   }
   const int64_t y = dsite(cx, dims);
-  const double2* xc = c.ws + b * c.ws_stride + c.xc_off + (3 * x + i) * c.R;
-  const double2* yt = c.ws + b * c.ws_stride + c.y_off + (3 * y + j) * c.R;
-  double2 s = make_double2(0.0, 0.0);
-  for (int k = 0; k < r; ++k) s = cfma(s, xc[k], yt[k]);
-  *out = csub(*out, s);
+  // the three rows of X C at site x and of Y^T at site y; each entry sums over k in order
+  const double2* xc = c.ws + b * c.ws_stride + c.xc_off + 3 * x * c.R;
+  const double2* yt = c.ws + b * c.ws_stride + c.y_off + 3 * y * c.R;
+  double2 s[9];
+#pragma unroll
+  for (int q = 0; q < 9; ++q) s[q] = make_double2(0.0, 0.0);
+  for (int k = 0; k < r; ++k) {
+    const double2 a0 = xc[k], a1 = xc[c.R + k], a2 = xc[2 * c.R + k];
+    const double2 b0 = yt[k], b1 = yt[c.R + k], b2 = yt[2 * c.R + k];
+    s[0] = cfma(s[0], a0, b0); s[1] = cfma(s[1], a0, b1); s[2] = cfma(s[2], a0, b2);
+    s[3] = cfma(s[3], a1, b0); s[4] = cfma(s[4], a1, b1); s[5] = cfma(s[5], a1, b2);
+    s[6] = cfma(s[6], a2, b0); s[7] = cfma(s[7], a2, b1); s[8] = cfma(s[8], a2, b2);
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) out[q] = csub(out[q], s[q]);
 }
 
 // Rows j_k of a solution x [N][ns] (device, per-configuration stride), into T [R][ns]

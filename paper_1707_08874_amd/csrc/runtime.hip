@@ -878,7 +878,7 @@ int enqueue_smw(cl_batch b) {
                      L.cfg_stride, P.pool_elems, b->ws, L.ws_elems, b->iws, L.iws_elems, nullptr, 0, b->d_inv,
                      nullptr, 0, true, b->iws + L.cnt_off, L.iws_elems);
   HIPCHK(hipGetLastError());
-  hipLaunchKernelGGL(clsel::k_smw_correct, dim3((unsigned)cdiv64(P.V * 81, 256), (unsigned)B), dim3(256), 0,
+  hipLaunchKernelGGL(clsel::k_smw_correct, dim3((unsigned)cdiv64(P.V * 9, 256), (unsigned)B), dim3(256), 0,
                      b->st, c, b->sel, ldims(P), P.V);
   HIPCHK(hipGetLastError());
   return 0;
