@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.8)
     ap.add_argument("--serve-seconds", type=float, default=20.0)
     ap.add_argument("--serve-burst", type=int, default=300)
+    ap.add_argument("--serve-max-slots", type=int, default=0,
+                    help="concurrent slots per lattice shape (0: the server's default)")
     ap.add_argument("--serve-slot-gb", type=float, default=0.0,
                     help="device memory a slot's batch may take (0: the server's default)")
     ap.add_argument("--gap-phases", action="store_true",
@@ -706,7 +708,12 @@ def serve(args):
     from parity import TOL, block_errors, drift_errors
 
     def run(reqs, label):
-        srv = Server(**({"slot_bytes_target": args.serve_slot_gb * 1e9} if args.serve_slot_gb > 0 else {}))
+        kw = {}
+        if args.serve_slot_gb > 0:
+            kw["slot_bytes_target"] = args.serve_slot_gb * 1e9
+        if args.serve_max_slots > 0:
+            kw["max_slots_per_shape"] = args.serve_max_slots
+        srv = Server(**kw)
         srv.warm(sorted({r.dims for r in reqs}))
         t = time.perf_counter()
         done = srv.run(reqs)
