@@ -9,10 +9,14 @@ and its accuracy is measured in two ways that need no reference solution: the
 largest per-block deviation of its selected blocks from the default plan's, and the
 residual of the diagonal blocks of D Z = 1, which only needs the selected blocks
 (row x of D reaches the sites x and x +- nu, whose blocks Z_{x+-nu,x} are selected).
-A candidate is accepted only if it deviates from the default by at most 1e-10 per
-block and its residual is no more than 1.25 times the default plan's; the fastest
-accepted one is stored, with these figures, in a JSON cache keyed by lattice shape and
-batch size. An entry marked "pinned" (set by hand) is never overwritten.
+The residual is the accuracy criterion: a candidate is accepted only if its residual
+is no more than 1.25 times the default plan's. The deviation only screens for a plan
+that computes something else (at most 1e-8 per block): the default plan's own blocks
+are off the exact inverse by a few 1e-10 on hard configurations, so a tighter bound on
+the deviation from them would turn away plans that are more accurate than the default.
+The fastest accepted candidate is stored, with these figures, in a JSON cache keyed by
+lattice shape and batch size. An entry marked "pinned" (set by hand) is never
+overwritten.
 
     python -m paper_1707_08874_amd.autotune --dims 8 8 8 4 --batch 64
 """
@@ -33,6 +37,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tuned.json")
 
 GRID = {"nb": (32, 64), "leaf_sites": (4, 12), "gemm_tile": (64, 12864, 128)}
+DEV_SCREEN = 1e-8  # largest accepted per-block deviation from the default plan
 
 
 def key(dims, batch) -> str:
@@ -120,8 +125,12 @@ def _block_dev(s, ref) -> float:
 
 
 def autotune(dims, batch, grid=None, reps=3, path: str | None = None, verbose=True,
-             force: bool = False) -> dict:
+             force: bool = False, base: dict | None = None) -> dict:
+    """Times the grid of plan options on (dims, batch) and stores the fastest accepted one.
+    `base` options (for example the pivot floor and low-rank cap) are applied to the default
+    plan and to every candidate, and stored with the choice."""
     import torch
+    base = dict(base or {})
     grid = grid or GRID
     dims = tuple(int(v) for v in dims)
     path = path or os.environ.get("CLSEL_TUNE_CACHE", DEFAULT_CACHE)
@@ -133,7 +142,7 @@ def autotune(dims, batch, grid=None, reps=3, path: str | None = None, verbose=Tr
         return cache[k]
     links = gen_batch(dims, range(batch))
     lt = torch.from_numpy(links).to("cuda")
-    t_def, s_def, d_def = _time_plan(torch, dims, batch, {}, lt, reps)
+    t_def, s_def, d_def = _time_plan(torch, dims, batch, dict(base), lt, reps)
     r_def = diagonal_residual(s_def, links, dims, 0.05, 0.25)
     results = [{"options": {}, "seconds": t_def, "residual": r_def, "max_dev_from_default": 0.0,
                 "ok": True}]
@@ -141,14 +150,14 @@ def autotune(dims, batch, grid=None, reps=3, path: str | None = None, verbose=Tr
     for vals in itertools.product(*(grid[n] for n in names)):
         opts = dict(zip(names, vals))
         try:
-            t, s, d = _time_plan(torch, dims, batch, opts, lt, reps)
+            t, s, d = _time_plan(torch, dims, batch, {**base, **opts}, lt, reps)
         except clsel.ClselError as e:  # e.g. over memory
             if verbose:
                 print(f"[tune] {opts}: {e}", flush=True)
             continue
         dev = _block_dev(s, s_def)
         res = diagonal_residual(s, links, dims, 0.05, 0.25)
-        ok = dev <= 1e-10 and res <= 1.25 * r_def
+        ok = dev <= DEV_SCREEN and res <= 1.25 * r_def
         results.append({"options": opts, "seconds": t, "max_dev_from_default": dev, "residual": res,
                         "ok": ok})
         if verbose:
@@ -161,7 +170,7 @@ def autotune(dims, batch, grid=None, reps=3, path: str | None = None, verbose=Tr
     near = [r for r in good if r["seconds"] <= 1.01 * fastest]
     best = min(near, key=lambda r: (r["residual"], not r["options"], r["seconds"]))
     cache = load(path)
-    cache[k] = {"options": best["options"], "seconds": best["seconds"], "default_seconds": t_def,
+    cache[k] = {"options": {**base, **best["options"]}, "seconds": best["seconds"], "default_seconds": t_def,
                 "candidates": len(results), "rejected": sum(not r["ok"] for r in results),
                 "residual": best["residual"], "default_residual": r_def,
                 "max_dev_from_default": best["max_dev_from_default"]}
@@ -177,8 +186,11 @@ def main(argv=None):
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=None, help="cache file (default: package tuned.json)")
     ap.add_argument("--force", action="store_true", help="retune an entry pinned by hand")
+    ap.add_argument("--base", type=json.loads, default=None,
+                    help='options applied to every plan, e.g. \'{"pivot_floor": 0.5, "lowrank_cap": 320}\'')
     args = ap.parse_args(argv)
-    print(json.dumps(autotune(args.dims, args.batch, reps=args.reps, path=args.out, force=args.force)))
+    print(json.dumps(autotune(args.dims, args.batch, reps=args.reps, path=args.out, force=args.force,
+                              base=args.base)))
 
 
 if __name__ == "__main__":
