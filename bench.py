@@ -498,9 +498,11 @@ def parity_sweep(args):
     sel, drift = sel[:K].cpu().numpy(), drift[:K].cpu().numpy()
     batch.close()
     # the plain single-configuration plan (graph replay), on the same configurations
+    # (options given on the command line apply to both plans)
     opts1 = autotune.options(dims, 1)
-    for key in ("pivot_floor", "lowrank_cap"):
-        if key in opts:
+    for key, given in (("nb", args.nb), ("leaf_sites", args.leaf), ("max_pivot_rows", args.max_pivot_rows),
+                       ("pivot_floor", args.pivot_floor), ("lowrank_cap", args.lowrank_cap)):
+        if given:
             opts1[key] = opts[key]
     pb = clsel.Batch(clsel.Plan(dims, **opts1), 1)
     pb.use_graph(True)
