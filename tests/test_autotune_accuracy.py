@@ -66,3 +66,15 @@ def test_pinned_entry_is_kept(tmp_path):
     p.write_text(json.dumps({"4x4x4x4|B1": {"options": {"nb": 32}, "pinned": True, "note": "hand"}}))
     out = autotune.autotune((4, 4, 4, 4), 1, path=str(p), verbose=False)
     assert out["options"] == {"nb": 32}
+
+
+def test_accept_rule():
+    """Kept only if no less accurate than the default by the residual and the same
+    computation (deviation within the screen); NaN figures are never accepted."""
+    r = 2e-11
+    assert autotune.accepted(3e-10, 1.4e-11, r)          # more accurate, deviates by rounding
+    assert autotune.accepted(0.0, r, r)
+    assert not autotune.accepted(0.0, 1.01 * r, r)       # less accurate
+    assert not autotune.accepted(1e-6, 1e-11, r)         # computes something else
+    assert not autotune.accepted(float("nan"), 1e-11, r)
+    assert not autotune.accepted(0.0, float("nan"), r)
