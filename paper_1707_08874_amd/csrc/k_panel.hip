@@ -35,8 +35,8 @@ constexpr int kPiLd = kMaxNB + 1;
 // kernel free of scratch spills.
 template <int RPT> struct PanelShape;
 template <> struct PanelShape<1> { static constexpr int G = 16, CH = 8; };
-template <> struct PanelShape<2> { static constexpr int G = 12, CH = 8; };
-template <> struct PanelShape<3> { static constexpr int G = 8, CH = 4; };
+template <> struct PanelShape<2> { static constexpr int G = 12, CH = 4; };
+template <> struct PanelShape<3> { static constexpr int G = 8, CH = 2; };
 
 // Cross-lane helpers for the pivot search. DPP moves stay in the vector ALU, so a
 // wave-wide reduction costs a few instructions per step and no LDS round trip.
@@ -241,33 +241,41 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
                                          : PW[(int64_t)(rest0 + cc) * cand + pr];
       }
       __syncthreads();
-      // the loads of a chunk of columns of all RPT rows are issued together, so that
-      // 8 * RPT loads per thread are in flight before the first product needs one
+      // Chunks of CH columns of all RPT rows, software-pipelined: the loads of the next
+      // chunk are issued before the products of the current one, so that their latency
+      // overlaps arithmetic (each chunk's loads otherwise wait a full memory round trip).
+      // They read columns the current chunk does not write.
       constexpr int kChunk = PanelShape<RPT>::CH;
-      for (int c0 = 0; c0 < nrest && !wave_dead; c0 += kChunk) {
-        double2 acc[RPT][kChunk];
+      // The loads are unconditional (addresses clamped into the panel, values of rows and
+      // columns outside it replaced by zero afterwards): no branch around them, so the
+      // wait before the products covers only the current chunk's loads.
+      auto load_chunk = [&](int c0, double2 (&a)[RPT][kChunk]) __attribute__((always_inline)) {
 #pragma unroll
         for (int j = 0; j < RPT; ++j) {
           const int r = tid + j * kPanelThreads;
           const bool ok = r < cand && !used[j];
-          const double2* src = g0 == 0 ? Xp + (int64_t)r * ld + rest0 + c0
-                                       : PW + (int64_t)(rest0 + c0) * cand + r;
-          const int64_t cs = g0 == 0 ? 1 : cand;
+          const int rc = r < cand ? r : 0;
 #pragma unroll
-          for (int q = 0; q < kChunk; ++q)
-            acc[j][q] = (ok && c0 + q < nrest) ? src[q * cs] : make_double2(0.0, 0.0);
+          for (int q = 0; q < kChunk; ++q) {
+            const int col = rest0 + min(c0 + q, nrest - 1);
+            const double2 v = g0 == 0 ? Xp[(int64_t)rc * ld + col] : PW[(int64_t)col * cand + rc];
+            a[j][q] = (ok && c0 + q < nrest) ? v : make_double2(0.0, 0.0);
+          }
         }
-        // each pivot-row value is read from LDS once per chunk and used for all RPT rows
-        // (the sum over t runs in the same order for every element)
+      };
+      // products and stores of one chunk (the sum over t runs in the same order for every
+      // element; each pivot-row value is read from LDS once and used for all RPT rows)
+      auto update_chunk = [&](int c0, double2 (&a)[RPT][kChunk]) __attribute__((always_inline)) {
 #pragma unroll
         for (int t = 0; t < kGroup; ++t) {
           if (t < gw) {
+            double2 rv[kChunk];
 #pragma unroll
-            for (int q = 0; q < kChunk; ++q) {
-              const double2 rv = s_buf[t * kMaxNB + min(c0 + q, nrest - 1)];
+            for (int q = 0; q < kChunk; ++q) rv[q] = s_buf[t * kMaxNB + min(c0 + q, nrest - 1)];
 #pragma unroll
-              for (int j = 0; j < RPT; ++j) acc[j][q] = cfma(acc[j][q], cur[j][t], rv);
-            }
+            for (int q = 0; q < kChunk; ++q)
+#pragma unroll
+              for (int j = 0; j < RPT; ++j) a[j][q] = cfma(a[j][q], cur[j][t], rv[q]);
           }
         }
 #pragma unroll
@@ -277,8 +285,21 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
             double2* dst = PW + (int64_t)(rest0 + c0) * cand + r;
 #pragma unroll
             for (int q = 0; q < kChunk; ++q)
-              if (c0 + q < nrest) dst[(int64_t)q * cand] = acc[j][q];
+              if (c0 + q < nrest) dst[(int64_t)q * cand] = a[j][q];
           }
+        }
+      };
+      // two register buffers in turn: the next chunk's loads are in flight during the
+      // current chunk's products
+      if (!wave_dead) {
+        double2 ca[RPT][kChunk], cb[RPT][kChunk];
+        load_chunk(0, ca);
+        for (int c0 = 0; c0 < nrest; c0 += 2 * kChunk) {
+          load_chunk(c0 + kChunk, cb);
+          update_chunk(c0, ca);
+          if (c0 + kChunk >= nrest) break;
+          load_chunk(c0 + 2 * kChunk, ca);
+          update_chunk(c0 + kChunk, cb);
         }
       }
       __syncthreads();
