@@ -321,34 +321,38 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
       v[q] = (live && cc < nbk) ? Xp[(int64_t)s_piv[t] * ld + cc] : make_double2(0.0, 0.0);
       if (live && cc == t) v[q] = cadd(v[q], s_delta[t]);  // the perturbed pivot, as in phase 1
     }
-    for (int c = 0; c < nbk; ++c) {
-      const int par = c & 1;
-      if (live && t == c) {
+    // Columns in blocks of eight, unrolled: column c = cb + qc is entry qc of the threads
+    // with cg = cb / 8, so every register index below is a constant.
+    for (int cb = 0; cb < nbk; cb += 8) {
+      const bool own = cg == (cb >> 3);  // this thread holds column c of its row
 #pragma unroll
-        for (int q = 0; q < 8; ++q) s_buf[par * kPiLd + cg * 8 + q] = v[q];
-      }
-      if (live && (c >> 3) == cg) {
+      for (int qc = 0; qc < 8; ++qc) {
+        const int c = cb + qc;
+        if (c < nbk) {  // uniform over the work-group
+          const int par = qc & 1;
+          if (live && t == c) {
 #pragma unroll
-        for (int q = 0; q < 8; ++q)
-          if (q == (c & 7)) s_pcol[par][t] = v[q];
-      }
-      __syncthreads();
-      double2 dp = s_buf[par * kPiLd + c];
-      if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) {
-        if (tid == 0) s_flag = 1;
-        dp = make_double2(1.0, 0.0);
-      }
-      const double2 invd = crecip(dp);
-      if (live) {
-        if (t == c) {
+            for (int q = 0; q < 8; ++q) s_buf[par * kPiLd + cg * 8 + q] = v[q];
+          }
+          if (live && own) s_pcol[par][t] = v[qc];
+          __syncthreads();
+          double2 dp = s_buf[par * kPiLd + c];
+          if (!(cabs2(dp) > 0.0) || !isfinite(dp.x) || !isfinite(dp.y)) {
+            if (tid == 0) s_flag = 1;
+            dp = make_double2(1.0, 0.0);
+          }
+          const double2 invd = crecip(dp);
+          if (live) {
+            if (t == c) {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) v[q] = (cg * 8 + q == c) ? invd : cmul(v[q], invd);
-        } else {
-          const double2 fi = cmul(s_pcol[par][t], invd);
+              for (int q = 0; q < 8; ++q) v[q] = (own && q == qc) ? invd : cmul(v[q], invd);
+            } else {
+              const double2 fi = cmul(s_pcol[par][t], invd);
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const int cc = cg * 8 + q;
-            v[q] = (cc == c) ? make_double2(-fi.x, -fi.y) : cfms(v[q], fi, s_buf[par * kPiLd + cc]);
+              for (int q = 0; q < 8; ++q)
+                v[q] = (own && q == qc) ? make_double2(-fi.x, -fi.y)
+                                        : cfms(v[q], fi, s_buf[par * kPiLd + cg * 8 + q]);
+            }
           }
         }
       }
