@@ -21,6 +21,14 @@ pytestmark = pytest.mark.gpu
 
 LATTICES = [(12, 12, 12, 6), (16, 16, 16, 8)]
 M = 0.05
+# Plan of the generic configuration. On 12^3x6 the pivot floor 0.5 (735 perturbed pivots,
+# within the cap of 1024) brings every sampled block and link within 1e-10, against 3.0e-10
+# at the library's default floor 0.3; on 16^3x8 the floor 0.4 already perturbs 1082 pivots,
+# beyond the largest cap, so it runs the default plan. The closed-form configurations run
+# the default plan on both.
+GENERIC_OPTS = {(12, 12, 12, 6): {"pivot_floor": 0.5, "lowrank_cap": 1024}, (16, 16, 16, 8): {}}
+XFAIL_1E10 = {(16, 16, 16, 8): "measured 4.9e-10 on some sampled blocks in the default plan: the "
+                               "double-precision floor of the static order at pivot floor 0.3"}
 
 
 @pytest.fixture(scope="module", params=LATTICES, ids=lambda d: "x".join(map(str, d)))
@@ -33,25 +41,33 @@ def results(request):
     U0 = unit_links(dims)
     Ug, g = pure_gauge_links(dims, 11, scale=0.2)  # kappa_1 bound 2.2e4 at 12^3x6 (scale 0.5: 4e7)
     Ur = gen_links(dims, 0, 0.1)
-    plan = clsel.Plan(dims)
-    # 12^3x6 runs the three configurations as one batch; 16^3x8 needs 221 GB of fronts
-    # per configuration, so one at a time
-    per = 3 if plan.bytes(3) < 100e9 else 1
     sel, drift, status = [], [], []
-    for i in range(0, 3, per):
-        print(f"\n[gpu] {dims}: configurations {i}..{i + per - 1} of (free, pure gauge, generic)",
+
+    def run(plan, links, first):
+        n = len(links)
+        print(f"\n[gpu] {dims}: configurations {first}..{first + n - 1} of (free, pure gauge, generic)",
               flush=True)
-        batch = clsel.Batch(plan, per)
-        lt = torch.from_numpy(np.stack([U0, Ug, Ur][i:i + per])).to("cuda")
+        batch = clsel.Batch(plan, n)
+        lt = torch.from_numpy(np.stack(links)).to("cuda")
         t0 = time.perf_counter()
         s, d = batch.run(lt, M, mu)
-        status += batch.status().tolist()
-        print(f"[gpu] {dims}: {per} configuration(s) in {time.perf_counter() - t0:.2f} s", flush=True)
+        status.extend(batch.status().tolist())
+        print(f"[gpu] {dims}: {n} configuration(s) in {time.perf_counter() - t0:.2f} s", flush=True)
         sel.append(s.cpu().numpy())
         drift.append(d.cpu().numpy())
         batch.close()
         del s, d, lt
         torch.cuda.empty_cache()
+
+    plan = clsel.Plan(dims)
+    # 12^3x6 runs the two closed-form configurations as one batch; 16^3x8 needs 166 GB of
+    # fronts per configuration, so one at a time
+    if plan.bytes(2) < 100e9:
+        run(plan, [U0, Ug], 0)
+    else:
+        run(plan, [U0], 0)
+        run(plan, [Ug], 1)
+    run(clsel.Plan(dims, **GENERIC_OPTS[dims]), [Ur], 2)
     return dict(dims=dims, mu=mu, sel=np.concatenate(sel), drift=np.concatenate(drift),
                 status=status, g=g, links=[U0, Ug, Ur])
 
@@ -80,8 +96,8 @@ def test_pure_gauge_every_block(results):
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-# Measured floor of double precision in the static elimination order on these lattices
-# (worst sampled block 3.0e-10 on 12^3x6, 4.9e-10 on 16^3x8); the bar 1e-10 is reported.
+# Regression floor: the worst sampled block is 8.5e-11 on 12^3x6 (pivot floor 0.5) and
+# 4.9e-10 on 16^3x8 (default plan), where the bar 1e-10 is reported.
 LARGE_FLOOR = 1e-9
 
 
@@ -108,12 +124,14 @@ def _sampled(results):
     return be, de
 
 
-@pytest.mark.xfail(strict=False, reason="measured above 1e-10 on some sampled blocks (3.0e-10 on 12^3x6, "
-                                        "4.9e-10 on 16^3x8): the double-precision floor of the static order")
 def test_generic_sampled_sites_within_1e_10(results):
-    """Every block and link drift the oracle computed around the sampled sites, at the bar."""
+    """Every block and link drift the oracle computed around the sampled sites, at the bar
+    (an expected failure on 16^3x8, whose plan cannot take the floor that gets there)."""
     be, de = _sampled(results)
-    assert be.max() <= TOL and de.max() <= TOL
+    ok = be.max() <= TOL and de.max() <= TOL
+    if not ok and results["dims"] in XFAIL_1E10:
+        pytest.xfail(XFAIL_1E10[results["dims"]])
+    assert ok
 
 
 def test_generic_sampled_sites_at_the_floor(results):
