@@ -109,8 +109,17 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   }
   const GemmDesc& d = descs[lo];
   const int64_t tile = (int64_t)bid - d.tile_start;
-  const int row0 = (int)(tile / d.tiles_n) * BM;
-  const int col0 = (int)(tile % d.tiles_n) * BN;
+  int row0 = (int)(tile / d.tiles_n) * BM;
+  int col0 = (int)(tile % d.tiles_n) * BN;
+  if constexpr (SOLVE) {
+    if (d.lim_dim == 1) {
+      // rows past the live count are cut: the tiles run rows fastest, so that the cut ones
+      // are spread over every XCD's range of tiles instead of filling the last XCDs' ranges
+      const int tiles_m = (d.M + BM - 1) / BM;
+      row0 = (int)(tile % tiles_m) * BM;
+      col0 = (int)(tile / tiles_m) * BN;
+    }
+  }
   // the product's extent; in the solves the right-hand sides past this configuration's
   // live count are neither read nor written (their columns or rows of the result stay
   // as they were; the kernels that read them skip them too)
