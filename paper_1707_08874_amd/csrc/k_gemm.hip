@@ -39,6 +39,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmThreads = 256;
 constexpr int kXcds = 8;
+constexpr int kGroupRows = 8;  // rows of tiles per group of the mode-0 raster
 
 struct GemmCtx {
   double2* fronts;
@@ -111,6 +112,18 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   const int64_t tile = (int64_t)bid - d.tile_start;
   int row0 = (int)(tile / d.tiles_n) * BM;
   int col0 = (int)(tile % d.tiles_n) * BN;
+  if constexpr (MODE == 0 && !SOLVE) {
+    // grouped raster: consecutive tiles walk down kGroupRows rows of tiles, then across,
+    // so that an XCD's contiguous range of tiles touches fewer operand panels (each XCD has
+    // its own L2)
+    const int tiles_m = (d.M + BM - 1) / BM;
+    const int64_t per_group = (int64_t)kGroupRows * d.tiles_n;
+    const int first = (int)(tile / per_group) * kGroupRows;
+    const int gm = min(tiles_m - first, kGroupRows);
+    const int in = (int)(tile % per_group);
+    row0 = (first + in % gm) * BM;
+    col0 = (in / gm) * BN;
+  }
   if constexpr (SOLVE) {
     if (d.lim_dim == 1) {
       // rows past the live count are cut: the tiles run rows fastest, so that the cut ones
