@@ -244,7 +244,8 @@ k_panel(const PanelDesc* __restrict__ descs, const double2* __restrict__ fronts,
       // Chunks of CH columns of all RPT rows, software-pipelined: the loads of the next
       // chunk are issued before the products of the current one, so that their latency
       // overlaps arithmetic (each chunk's loads otherwise wait a full memory round trip).
-      // They read columns the current chunk does not write.
+      // They read columns the current chunk does not write, except the clamped reads past
+      // the last column, whose values are discarded.
       constexpr int kChunk = PanelShape<RPT>::CH;
       // The loads are unconditional (addresses clamped into the panel, values of rows and
       // columns outside it replaced by zero afterwards): no branch around them, so the
