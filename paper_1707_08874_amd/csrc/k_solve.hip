@@ -12,7 +12,7 @@
 // The products are GEMM launches; the kernels here move rows between fronts.
 // One thread per (row, column) element; consecutive threads take consecutive elements of
 // the front block's storage: consecutive columns of a row (right solves) or consecutive
-// rows of a column (left solves).
+// rows of a column (left solves); the scatter of the solution follows its output instead.
 // Left solves (row vectors, W D = G) run the transposed recurrences with the same
 // factors: forward G_f[S] -= G_f[J] U^, backward W_J = G_J A_JJ^{-1} - W_S L^, on front
 // blocks stored n x H (TRANS).
@@ -106,8 +106,10 @@ k_sol_scatter(const SolScatterDesc* __restrict__ descs, int ndesc, const double2
   const SolScatterDesc& d = descs[find_desc(descs, ndesc, (int64_t)blockIdx.x)];
   const int64_t e = ((int64_t)blockIdx.x - d.blk_start) * 256 + threadIdx.x;
   if (e >= (int64_t)d.p * ns) return;
+  // threads follow the output (rows of x, ns values each), so that the writes are
+  // contiguous; a left solve's block is then read across its stored columns
   int I, col;
-  elem_rc<TRANS>(e, d.p, ns, I, col);
+  elem_rc<false>(e, d.p, ns, I, col);
   const int site = front_sites[d.site_off + I / 3];
   double2* dst = x + cfg * x_stride + ((int64_t)site * 3 + I % 3) * ns + col;
   if (lim && col >= lim[cfg * lim_stride]) {  // the solution of a zero right-hand side
