@@ -311,6 +311,8 @@ k_smw_correct(SmwCtx c, double2* __restrict__ sel, LatticeDims dims, int64_t V) 
   double2 s[9];
 #pragma unroll
   for (int q = 0; q < 9; ++q) s[q] = make_double2(0.0, 0.0);
+  // (unrolled: the loads of several k are in flight together; the order of each sum is kept)
+#pragma unroll 4
   for (int k = 0; k < r; ++k) {
     const double2 a0 = xc[k], a1 = xc[c.R + k], a2 = xc[2 * c.R + k];
     const double2 b0 = yt[k], b1 = yt[c.R + k], b2 = yt[2 * c.R + k];
