@@ -65,22 +65,29 @@ __device__ __forceinline__ double2* pool_ptr(const GemmCtx& g, int b, int pool) 
   return g.fronts + b * g.cfg_stride + (int64_t)pool * g.pool_elems;
 }
 
-// Per-thread operand sources, fixed for the whole K loop.
+// Per-thread operand sources, fixed for the whole K loop. In modes 1 and 2 the descriptor
+// fields the loads need are copied here once: read through the descriptor in global memory,
+// they would be loaded again at every stage (the loop's stores might alias it), each load
+// followed by a wait that also holds the stage's LDS reads. Mode 0 reads its one field, the
+// leading dimension of B, from the descriptor: it has no registers to spare for it.
 template <int MODE, int RA>
 struct Operands {
   const double2* arow[RA];  // A rows handled by this thread (nullptr: zero or special)
   int ai[RA];               // A row index (global)
   const double2* bbase;     // B base
+  int64_t ldb;              // B leading dimension (mode 2)
+  int k, nbk, row_base;     // the step's pivot block and first row (modes 1 and 2)
+  int ld;                   // leading dimension of the front (mode 1)
+  const int32_t* piv;       // the step's pivot rows (mode 1)
 };
 
 template <int MODE, int RA>
-__device__ __forceinline__ double2 ld_a(const GemmDesc& d, const Operands<MODE, RA>& o, int r, int t,
-                                       int Mv, int Kv) {
+__device__ __forceinline__ double2 ld_a(const Operands<MODE, RA>& o, int r, int t, int Mv, int Kv) {
   const double2 z = make_double2(0.0, 0.0);
   if (t >= Kv || o.ai[r] >= Mv) return z;
   if (MODE == 2) {
-    const int i = o.ai[r] + d.row_base;
-    if (i >= d.k && i < d.k + d.nbk) return make_double2(i - d.k == t ? -1.0 : 0.0, 0.0);
+    const int i = o.ai[r] + o.row_base;
+    if (i >= o.k && i < o.k + o.nbk) return make_double2(i - o.k == t ? -1.0 : 0.0, 0.0);
   }
   return o.arow[r][t];
 }
@@ -181,6 +188,14 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
   if (MODE == 0) o.bbase = pool_ptr(g, b, d.b_pool) + d.b_off;
   else if (MODE == 1) o.bbase = F + d.x_off;
   else o.bbase = W + d.rt_off;
+  if constexpr (MODE != 0) {
+    o.ldb = d.ldb;
+    o.k = d.k;
+    o.nbk = d.nbk;
+    o.row_base = d.row_base;
+    o.ld = d.ld;
+    o.piv = IW + d.piv_off;
+  }
 
   auto ld_b = [&](int t) __attribute__((always_inline)) -> double2 {
     const double2 z = make_double2(0.0, 0.0);
@@ -188,10 +203,10 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
     if (t >= Kv || j >= Nv) return z;
     if (MODE == 0) return o.bbase[(int64_t)t * d.ldb + j];
     if (MODE == 1) {
-      if (j >= d.k && j < d.k + d.nbk) return make_double2(j - d.k == t ? 1.0 : 0.0, 0.0);
-      return o.bbase[(int64_t)IW[d.piv_off + t] * d.ld + j];
+      if (j >= o.k && j < o.k + o.nbk) return make_double2(j - o.k == t ? 1.0 : 0.0, 0.0);
+      return o.bbase[(int64_t)o.piv[t] * o.ld + j];
     }
-    return o.bbase[(int64_t)t * d.ldb + j];
+    return o.bbase[(int64_t)t * o.ldb + j];
   };
 
   d4 cr[TM][TN], ci[TM][TN];
@@ -238,7 +253,7 @@ k_gemm(const GemmDesc* __restrict__ descs, int ndesc, GemmCtx g) {
 
   auto load_stage = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
-    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(d, o, r, k0 + a_kk, Mv, Kv);
+    for (int r = 0; r < RA; ++r) pa[r] = ld_a<MODE, RA>(o, r, k0 + a_kk, Mv, Kv);
 #pragma unroll
     for (int r = 0; r < RB; ++r) pb[r] = ld_b(k0 + b_kk0 + b_kstep * r);
   };
